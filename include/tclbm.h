@@ -1,0 +1,175 @@
+/*
+ * tclbm.h -- C ABI of the MI355X (gfx950) thermal cascaded lattice Boltzmann
+ * library libtclbm.so.
+ *
+ * The library advances the two D2Q9 distribution functions of the thermal
+ * cascaded lattice Boltzmann method of Fei & Luo (arXiv:1610.07114): the
+ * density DF f, relaxed by the cascaded (central-moment) collision with
+ * central-moment forcing (Sections 2-3) and the third-moment correction term
+ * C (Section 4), and the total-energy DF h, relaxed towards its equilibrium
+ * with the coupling source K (Section 4).  Both are pull-streamed.  Every step
+ * is one fused HIP kernel launch on the handle's stream.
+ *
+ * Conventions
+ *   - Lattice units: R*T0 must be 1/3 (c_s^2); the default R = 1/3, T0 = 1.
+ *   - Host fields are float64 arrays of nx*ny values, index y*nx + x.
+ *   - D2Q9 order (Section 2): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+ *   - No C++ types or exceptions cross this interface.  Every function returns
+ *     a tclbm_status (or a size / string); nothing aborts the process.
+ *   - A handle may be used from one host thread at a time.  Work is enqueued
+ *     on the stream given at creation; functions that return host data
+ *     (tclbm_moments, tclbm_step_timed) synchronise that stream.
+ *
+ * Ownership
+ *   - dev_buf passed to tclbm_create is caller-owned device memory (for
+ *     example a torch tensor's storage) of at least tclbm_state_bytes() bytes;
+ *     the library borrows it until tclbm_destroy and never frees it.
+ *   - The stream is borrowed.  Host arrays are read (copied) during the call.
+ *   - The handle owns a small device buffer for macroscopic output fields,
+ *     allocated on the first tclbm_moments call that asks for fields.
+ */
+#ifndef TCLBM_H
+#define TCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tclbm_ctx *tclbm_handle;
+
+typedef enum {
+  TCLBM_OK = 0,
+  TCLBM_E_INVALID = 1,  /* bad argument or parameter; nothing was changed   */
+  TCLBM_E_NOMEM = 2,    /* dev_bytes too small or an internal allocation failed */
+  TCLBM_E_DEVICE = 3,   /* a HIP runtime call failed (message: tclbm_last_error) */
+  TCLBM_E_STATE = 4,    /* handle unusable (failed create or earlier instability) */
+  TCLBM_E_UNSTABLE = 5  /* non-finite or non-positive density/temperature found */
+} tclbm_status;
+
+/* Storage of f and h in device memory.  Arithmetic is FP32 for the first
+ * three and FP64 for the last.  The 16-bit forms store each population as its
+ * deviation from a per-row rest-state equilibrium (computed at create time from
+ * the row means of the initial density and temperature). */
+typedef enum {
+  TCLBM_STORE_F32 = 0,
+  TCLBM_STORE_F16_DEV = 1,
+  TCLBM_STORE_BF16_DEV = 2,
+  TCLBM_STORE_F64 = 3
+} tclbm_storage;
+
+typedef enum { TCLBM_XLO = 0, TCLBM_XHI = 1, TCLBM_YLO = 2, TCLBM_YHI = 3 } tclbm_side;
+
+/* Boundary kinds.  PERIODIC must be set on both sides of an axis or neither.
+ * BOUNCEBACK: halfway bounce-back at rest (adiabatic for h), any side.
+ * WALL: node wall on the boundary row (y sides only) imposing (ux_w, uy_w, T_w)
+ * by non-equilibrium extrapolation of both DFs from the adjacent fluid node. */
+typedef enum { TCLBM_BC_PERIODIC = 0, TCLBM_BC_BOUNCEBACK = 1, TCLBM_BC_WALL = 2 } tclbm_bc_kind;
+
+typedef struct {
+  int32_t nx, ny;        /* lattice size, each >= 3 */
+  double R, T0;          /* gas constant and reference temperature, R*T0 = 1/3 */
+  double gamma, Pr;      /* specific-heat ratio (> 1) and Prandtl number (> 0) */
+  double tau_f;          /* 1/w1 (> 0.5): mu = p (tau_f - 1/2), Eq. (29) */
+  double w2, w3, w4;     /* bulk, third- and fourth-order rates, in (0, 2) */
+  double ax, ay;         /* uniform body acceleration (force density rho a) */
+  int32_t thermal;       /* 1: TCLBM; 0: athermal cascaded LBM (T = T0, no h) */
+  int32_t correction;    /* 1: include the correction term C_a (Section 4) */
+  int32_t storage;       /* tclbm_storage */
+  int32_t wall_rho;      /* wall-node density: 0 from the populations that reached
+                            the wall node (default), 1 the fluid neighbour's,
+                            2 the fluid neighbour's pressure plus rho a.n */
+  int32_t heq_moments;   /* h^eq moments beyond second order: 0 continuous
+                            Maxwellian values (default), 1 raw zero (Section 4's
+                            explicit form) */
+  int32_t h_collision;   /* energy DF update: 0 two-rate (energy flux at w_h,
+                            other moments at 1; default), 1 BGK (Section 4) */
+  int32_t accel_field;   /* 1: tclbm_create receives per-node acceleration
+                            arrays (space for them is part of the state) */
+} tclbm_params;
+
+/* FP64 whole-lattice reductions of the state the next step would see
+ * (Eq. (20) and the temperature of Section 4). */
+typedef struct {
+  double mass;       /* sum rho */
+  double momx, momy; /* sum rho u */
+  double energy;     /* sum of hbar = sum rho E */
+  double kinetic;    /* sum rho u^2 / 2 */
+  double nu_num;     /* sum u_y (T - T0)  (Nusselt numerator, Section 5D) */
+  double rho_min, T_min;
+  int64_t nonfinite; /* nodes with non-finite rho, u or T */
+} tclbm_sums;
+
+/* Fill *p with defaults: R = 1/3, T0 = 1, gamma = 1.4, Pr = 0.71, tau_f = 0.8,
+ * w2 = w3 = w4 = 1, no force, thermal with correction, FP32 storage. */
+void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p);
+
+/* Exact device bytes tclbm_create needs in dev_buf for these parameters
+ * (two ping-pong population buffers, per-row reference tables, force field
+ * and reduction scratch), or 0 if the parameters are invalid. */
+size_t tclbm_state_bytes(const tclbm_params *p);
+
+/* Validate p, lay out dev_buf, upload the initial macroscopic fields and
+ * initialise fbar = f^eq - S/2, hbar = h^eq (Sections 3-4) on the stream.
+ * rho, ux, uy, T: host, nx*ny each (T ignored when thermal = 0).
+ * ax_field, ay_field: host per-node acceleration (nullable; when given they
+ * replace the uniform ax, ay).  hip_stream: a hipStream_t (NULL: default).
+ * All sides start PERIODIC.  On error *out is NULL and nothing is kept. */
+tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                          const double *rho, const double *ux, const double *uy, const double *T,
+                          const double *ax_field, const double *ay_field, tclbm_handle *out);
+
+/* Set the boundary kind of one side and, for WALL, its velocity and
+ * temperature.  Takes effect from the next step.  E_INVALID for WALL on an x
+ * side, a periodic side whose opposite is not periodic after the call (set
+ * both sides of an axis before stepping: the pair is checked at step time). */
+tclbm_status tclbm_set_bc(tclbm_handle h, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w);
+
+/* Enqueue nsteps time steps (asynchronous).  Long runs replay a captured HIP
+ * graph of a fixed chunk of steps.  E_INVALID for an unpaired periodic axis. */
+tclbm_status tclbm_step(tclbm_handle h, int64_t nsteps);
+
+/* As tclbm_step, then synchronise and report the elapsed device time of the
+ * enqueued steps (HIP events recorded on the handle's stream). */
+tclbm_status tclbm_step_timed(tclbm_handle h, int64_t nsteps, double *ms);
+
+/* Macroscopic fields (host float64, nx*ny each; any pointer may be NULL) and
+ * FP64 sums of the current state.  Synchronises.  Returns E_UNSTABLE (fields
+ * and sums still written) when a node is non-finite or has rho <= 0 or
+ * T <= 0; the handle then refuses further steps with E_STATE. */
+tclbm_status tclbm_moments(tclbm_handle h, double *rho, double *ux, double *uy, double *T, tclbm_sums *sums);
+
+/* Number of time steps taken so far. */
+int64_t tclbm_steps_done(tclbm_handle h);
+
+/* Copy the raw post-collision population planes of the current state to the
+ * host, in storage order [2][9][ny][nx] (f then h; h planes omitted when
+ * thermal = 0), converted to float64 (16-bit forms: reference added back).
+ * out must hold 18*nx*ny doubles (9*nx*ny when athermal).  Synchronises. */
+tclbm_status tclbm_read_state(tclbm_handle h, double *out);
+
+/* Launch shape of the step kernel: rows per wave strip (>= 1; 0 = automatic)
+ * and steps per captured HIP graph (even, >= 2; 0 = no graphs).  Results do not
+ * depend on either (every node runs the same arithmetic). */
+tclbm_status tclbm_set_tuning(tclbm_handle h, int32_t strip_rows, int32_t graph_chunk);
+
+/* Release the handle (waits for its stream).  dev_buf is not freed. */
+tclbm_status tclbm_destroy(tclbm_handle h);
+
+/* Diagnostic: enqueue one plain streaming copy of `bytes` (multiple of 16,
+ * 16-byte aligned device pointers, non-overlapping) on the stream.  Used to
+ * measure the achievable HBM bandwidth next to the step kernel and to scale
+ * hardware byte counters. */
+tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Static string for a status code; last HIP/validation message of a handle. */
+const char *tclbm_status_str(tclbm_status s);
+const char *tclbm_last_error(tclbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCLBM_H */

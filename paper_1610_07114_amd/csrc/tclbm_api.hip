@@ -1,0 +1,539 @@
+// tclbm_api.hip -- host side of the C ABI declared in include/tclbm.h:
+// parameter validation and derivation, the memory plan inside the caller's
+// device buffer, initial state, stepping (with HIP-graph replay of fixed step
+// chunks), FP64 moments and error reporting.  Every HIP failure becomes a
+// status code; nothing here aborts.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/tclbm.h"
+#include "tclbm_internal.h"
+#include "tclbm_node.h"
+
+using namespace tclbm;
+
+struct tclbm_ctx {
+  tclbm_params p;
+  KParams k;             // template for launches (src/dst filled per step)
+  hipStream_t stream;
+  char *base;
+  void *buf[2];
+  int cur;               // index of the buffer holding the current state
+  size_t esz;
+  double *partials;
+  int nparts;
+  double *fields;        // library-owned, lazily allocated (4 * n doubles)
+  int64_t steps;
+  bool unstable;
+  int strip_rows_req;
+  int graph_chunk;
+  hipGraphExec_t graph;  // replays graph_chunk steps starting from buffer 0
+  bool graph_ok;
+  char err[512];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void set_err(tclbm_ctx *c, const char *fmt, ...) {
+  if (!c) return;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(c->err, sizeof(c->err), fmt, ap);
+  va_end(ap);
+}
+
+bool valid_params(const tclbm_params *p) {
+  if (!p) return false;
+  if (p->nx < 3 || p->ny < 3) return false;
+  if ((long long)p->nx * p->ny > (1LL << 28)) return false;
+  if (!(std::isfinite(p->R) && std::isfinite(p->T0) && p->R > 0 && p->T0 > 0)) return false;
+  if (std::fabs(p->R * p->T0 - 1.0 / 3.0) > 1e-12) return false;
+  if (!(p->gamma > 1.0) || !(p->Pr > 0.0) || !std::isfinite(p->gamma) || !std::isfinite(p->Pr)) return false;
+  if (!(p->tau_f > 0.5) || !std::isfinite(p->tau_f)) return false;
+  for (double w : {p->w2, p->w3, p->w4})
+    if (!(w > 0.0 && w < 2.0)) return false;
+  if (!std::isfinite(p->ax) || !std::isfinite(p->ay)) return false;
+  if (p->thermal != 0 && p->thermal != 1) return false;
+  if (p->correction != 0 && p->correction != 1) return false;
+  if (p->storage < kF32 || p->storage > kF64) return false;
+  if (p->wall_rho < 0 || p->wall_rho > 2) return false;
+  if (p->heq_moments < 0 || p->heq_moments > 1) return false;
+  if (p->h_collision < 0 || p->h_collision > 1) return false;
+  if (p->accel_field != 0 && p->accel_field != 1) return false;
+  return true;
+}
+
+int pitch_of(const tclbm_params *p) { return (int)up((size_t)p->nx, 64); }
+int planes_of(const tclbm_params *p) { return p->thermal ? 18 : 9; }
+
+struct Plan {
+  size_t buf, ref, acc, part, total;
+};
+
+Plan plan_of(const tclbm_params *p) {
+  Plan pl;
+  const size_t esz = store_bytes(p->storage);
+  const size_t plane = (size_t)pitch_of(p) * p->ny;
+  pl.buf = up(plane * planes_of(p) * esz, kAlign);
+  pl.ref = up(sizeof(float) * 2 * 9 * (size_t)p->ny, kAlign);
+  const size_t rsz = (p->storage == kF64) ? 8 : 4;
+  pl.acc = p->accel_field ? up(2 * plane * rsz, kAlign) : 0;
+  const long long n = (long long)p->nx * p->ny;
+  pl.part = up(sizeof(double) * kNumSums * (size_t)((n + 255) / 256), kAlign);
+  pl.total = 2 * pl.buf + pl.ref + pl.acc + pl.part;
+  return pl;
+}
+
+// Derived relaxation constants (Sections 4-5): b from gamma, w1 = 1/tau_f,
+// 1/w_h = (1/w1 - 1/2)/Pr + 1/2, 1/tau_hf = w1 (Pr - 1).
+void fill_kparams(tclbm_ctx *c) {
+  const tclbm_params &p = c->p;
+  KParams &k = c->k;
+  memset(&k, 0, sizeof(k));
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.pitch = pitch_of(&p);
+  k.plane = (long long)k.pitch * p.ny;
+  k.thermal = p.thermal;
+  k.correction = p.correction;
+  k.heq_mode = p.heq_moments;
+  k.h_coll = p.h_collision;
+  k.wall_rho = p.wall_rho;
+  k.R = p.R;
+  k.T0 = p.T0;
+  k.b = 2.0 / (p.gamma - 1.0);
+  k.w1 = 1.0 / p.tau_f;
+  k.w2 = p.w2;
+  k.w3 = p.w3;
+  k.w4 = p.w4;
+  k.wh = 1.0 / ((p.tau_f - 0.5) / p.Pr + 0.5);
+  k.inv_tau_hf = k.w1 * (p.Pr - 1.0);
+  k.ax = p.ax;
+  k.ay = p.ay;
+  for (int s = 0; s < 4; ++s) {
+    k.bc[s] = kPeriodic;
+    k.wall_T[s] = p.T0;
+  }
+}
+
+void decompose(tclbm_ctx *c) {
+  KParams &k = c->k;
+  const bool xper = k.bc[kXlo] == kPeriodic;
+  k.lane_off = xper ? 1 : 2;
+  k.tile_w = 64 - 1 - k.lane_off;
+  k.n_xtiles = (k.nx + k.tile_w - 1) / k.tile_w;
+  int rows = c->strip_rows_req;
+  if (rows <= 0) {
+    // enough waves to fill 256 CUs several times over, strips of >= 4 rows
+    const long long target = 16384;
+    long long r = ((long long)k.ny * k.n_xtiles + target - 1) / target;
+    rows = (int)(r < 4 ? 4 : r);
+  }
+  if (rows > k.ny) rows = k.ny;
+  k.strip_rows = rows;
+  k.n_strips = (k.ny + rows - 1) / rows;
+}
+
+bool bc_pairs_ok(const KParams &k) {
+  if ((k.bc[kXlo] == kPeriodic) != (k.bc[kXhi] == kPeriodic)) return false;
+  if ((k.bc[kYlo] == kPeriodic) != (k.bc[kYhi] == kPeriodic)) return false;
+  return true;
+}
+
+#define HIP_TRY(ctx, expr)                                                    \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      set_err(ctx, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+      return TCLBM_E_DEVICE;                                                  \
+    }                                                                         \
+  } while (0)
+
+// Host copy of the product-form density equilibrium and of the energy
+// equilibrium at rest, for the 16-bit reference rows.
+void rest_refs(const tclbm_params &p, double rho, double T, float *rf, float *rh) {
+  double f[9], h[9];
+  const double RT = p.R * T;
+  feq9<double>(rho, 0.0, 0.0, RT, f);
+  heq9<double>(rho, 0.0, 0.0, RT, 2.0 / (p.gamma - 1.0), p.heq_moments, h);
+  for (int a = 0; a < 9; ++a) {
+    rf[a] = (float)f[a];
+    rh[a] = p.thermal ? (float)h[a] : 0.0f;
+  }
+}
+
+tclbm_status launch_steps(tclbm_ctx *c, int64_t n) {
+  for (int64_t s = 0; s < n; ++s) {
+    KParams k = c->k;
+    k.src = c->buf[c->cur];
+    k.dst = c->buf[1 - c->cur];
+    HIP_TRY(c, launch_step(k, c->p.storage, c->stream));
+    c->cur = 1 - c->cur;
+    ++c->steps;
+  }
+  return TCLBM_OK;
+}
+
+void drop_graph(tclbm_ctx *c) {
+  if (c->graph_ok) hipGraphExecDestroy(c->graph);
+  c->graph_ok = false;
+}
+
+tclbm_status build_graph(tclbm_ctx *c) {
+  drop_graph(c);
+  hipGraph_t g;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t lerr = hipSuccess;
+  for (int s = 0; s < c->graph_chunk && lerr == hipSuccess; ++s) {
+    KParams k = c->k;
+    k.src = c->buf[s & 1];
+    k.dst = c->buf[1 - (s & 1)];
+    lerr = launch_step(k, c->p.storage, c->stream);
+  }
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (lerr != hipSuccess || e != hipSuccess) {
+    set_err(c, "graph capture failed: %s", hipGetErrorString(lerr != hipSuccess ? lerr : e));
+    if (e == hipSuccess) hipGraphDestroy(g);
+    return TCLBM_E_DEVICE;
+  }
+  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    set_err(c, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return TCLBM_E_DEVICE;
+  }
+  c->graph_ok = true;
+  return TCLBM_OK;
+}
+
+tclbm_status do_steps(tclbm_ctx *c, int64_t n) {
+  if (!c) return TCLBM_E_INVALID;
+  if (c->unstable) return TCLBM_E_STATE;
+  if (n < 0) return TCLBM_E_INVALID;
+  if (!bc_pairs_ok(c->k)) {
+    set_err(c, "periodic sides must come in pairs");
+    return TCLBM_E_INVALID;
+  }
+  const int ch = c->graph_chunk;
+  if (ch >= 2 && n >= 2 * (int64_t)ch) {
+    if (c->cur != 0) {
+      tclbm_status st = launch_steps(c, 1);
+      if (st != TCLBM_OK) return st;
+      --n;
+    }
+    if (!c->graph_ok) {
+      tclbm_status st = build_graph(c);
+      if (st != TCLBM_OK) return st;
+    }
+    while (n >= ch) {
+      HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+      c->steps += ch;
+      n -= ch;
+    }
+  }
+  return launch_steps(c, n);
+}
+
+}  // namespace
+
+extern "C" {
+
+void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->nx = nx;
+  p->ny = ny;
+  p->R = 1.0 / 3.0;
+  p->T0 = 1.0;
+  p->gamma = 1.4;
+  p->Pr = 0.71;
+  p->tau_f = 0.8;
+  p->w2 = p->w3 = p->w4 = 1.0;
+  p->thermal = 1;
+  p->correction = 1;
+  p->storage = TCLBM_STORE_F32;
+}
+
+size_t tclbm_state_bytes(const tclbm_params *p) {
+  if (!valid_params(p)) return 0;
+  return plan_of(p).total;
+}
+
+tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                          const double *rho, const double *ux, const double *uy, const double *T,
+                          const double *ax_field, const double *ay_field, tclbm_handle *out) {
+  if (!out) return TCLBM_E_INVALID;
+  *out = nullptr;
+  if (!valid_params(p) || !dev_buf || !rho || !ux || !uy || (p->thermal && !T)) return TCLBM_E_INVALID;
+  if ((p->accel_field != 0) != (ax_field != nullptr && ay_field != nullptr)) return TCLBM_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(dev_buf) & (kAlign - 1)) != 0) return TCLBM_E_INVALID;
+  const Plan pl = plan_of(p);
+  if (dev_bytes < pl.total) return TCLBM_E_NOMEM;
+  const long long n = (long long)p->nx * p->ny;
+  for (long long i = 0; i < n; ++i) {
+    if (!(std::isfinite(rho[i]) && rho[i] > 0 && std::isfinite(ux[i]) && std::isfinite(uy[i])))
+      return TCLBM_E_INVALID;
+    if (p->thermal && !(std::isfinite(T[i]) && T[i] > 0)) return TCLBM_E_INVALID;
+    if (ax_field && !(std::isfinite(ax_field[i]) && std::isfinite(ay_field[i]))) return TCLBM_E_INVALID;
+  }
+
+  tclbm_ctx *c = new (std::nothrow) tclbm_ctx();
+  if (!c) return TCLBM_E_NOMEM;
+  c->p = *p;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->base = reinterpret_cast<char *>(dev_buf);
+  c->esz = store_bytes(p->storage);
+  c->buf[0] = c->base;
+  c->buf[1] = c->base + pl.buf;
+  float *refs = reinterpret_cast<float *>(c->base + 2 * pl.buf);
+  char *acc = c->base + 2 * pl.buf + pl.ref;
+  c->partials = reinterpret_cast<double *>(acc + pl.acc);
+  c->nparts = (int)((n + 255) / 256);
+  c->cur = 0;
+  c->graph_chunk = 32;
+  fill_kparams(c);
+  c->k.refF = refs;
+  c->k.refH = refs + 9 * p->ny;
+  decompose(c);
+
+  tclbm_status st = TCLBM_OK;
+  double *tmp = nullptr;
+  do {
+    // per-row rest-state references (used by the 16-bit storage forms)
+    std::vector<float> ref(2 * 9 * (size_t)p->ny);
+    for (int y = 0; y < p->ny; ++y) {
+      double rs = 0, ts = 0;
+      for (int x = 0; x < p->nx; ++x) {
+        rs += rho[(size_t)y * p->nx + x];
+        ts += p->thermal ? T[(size_t)y * p->nx + x] : p->T0;
+      }
+      rest_refs(*p, rs / p->nx, ts / p->nx, &ref[(size_t)y * 9], &ref[(size_t)(p->ny + y) * 9]);
+    }
+    hipError_t e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) { set_err(c, "ref upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
+    if (p->accel_field) {
+      const size_t plane = (size_t)c->k.plane;
+      if (p->storage == kF64) {
+        std::vector<double> a(2 * plane, 0.0);
+        for (int y = 0; y < p->ny; ++y)
+          for (int x = 0; x < p->nx; ++x) {
+            a[(size_t)y * c->k.pitch + x] = ax_field[(size_t)y * p->nx + x];
+            a[plane + (size_t)y * c->k.pitch + x] = ay_field[(size_t)y * p->nx + x];
+          }
+        e = hipMemcpyAsync(acc, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        c->k.axf = acc;
+        c->k.ayf = acc + plane * sizeof(double);
+      } else {
+        std::vector<float> a(2 * plane, 0.0f);
+        for (int y = 0; y < p->ny; ++y)
+          for (int x = 0; x < p->nx; ++x) {
+            a[(size_t)y * c->k.pitch + x] = (float)ax_field[(size_t)y * p->nx + x];
+            a[plane + (size_t)y * c->k.pitch + x] = (float)ay_field[(size_t)y * p->nx + x];
+          }
+        e = hipMemcpyAsync(acc, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        c->k.axf = acc;
+        c->k.ayf = acc + plane * sizeof(float);
+      }
+      if (e != hipSuccess) { set_err(c, "accel upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
+    }
+    // stage the initial fields and build the pre-pulled initial state
+    e = hipMalloc(&tmp, sizeof(double) * 4 * (size_t)n);
+    if (e != hipSuccess) { set_err(c, "hipMalloc: %s", hipGetErrorString(e)); st = TCLBM_E_NOMEM; tmp = nullptr; break; }
+    const double *srcs[4] = {rho, ux, uy, p->thermal ? T : rho};
+    for (int q = 0; q < 4 && e == hipSuccess; ++q)
+      e = hipMemcpyAsync(tmp + (size_t)q * n, srcs[q], sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) { set_err(c, "field upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
+    KParams k = c->k;
+    k.dst = c->buf[0];
+    e = launch_init(k, p->storage, tmp, tmp + n, tmp + 2 * n, tmp + 3 * n, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { set_err(c, "init: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
+  } while (0);
+  if (tmp) hipFree(tmp);
+  if (st != TCLBM_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_set_bc(tclbm_handle c, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w) {
+  if (!c) return TCLBM_E_INVALID;
+  if (side < 0 || side > 3 || kind < 0 || kind > 2) return TCLBM_E_INVALID;
+  if (kind == kWall && side < kYlo) {
+    set_err(c, "WALL is supported on y sides only");
+    return TCLBM_E_INVALID;
+  }
+  if (!(std::isfinite(ux_w) && std::isfinite(uy_w) && std::isfinite(T_w)) || (kind == kWall && !(T_w > 0)))
+    return TCLBM_E_INVALID;
+  c->k.bc[side] = kind;
+  c->k.wall_ux[side] = ux_w;
+  c->k.wall_uy[side] = uy_w;
+  c->k.wall_T[side] = (kind == kWall) ? T_w : c->p.T0;
+  decompose(c);
+  drop_graph(c);
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_set_tuning(tclbm_handle c, int32_t strip_rows, int32_t graph_chunk) {
+  if (!c || strip_rows < 0 || graph_chunk < 0 || graph_chunk == 1 || (graph_chunk & 1)) return TCLBM_E_INVALID;
+  c->strip_rows_req = strip_rows;
+  c->graph_chunk = graph_chunk;
+  decompose(c);
+  drop_graph(c);
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_step(tclbm_handle c, int64_t nsteps) { return do_steps(c, nsteps); }
+
+tclbm_status tclbm_step_timed(tclbm_handle c, int64_t nsteps, double *ms) {
+  if (!c || !ms) return TCLBM_E_INVALID;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return TCLBM_E_DEVICE;
+  }
+  tclbm_status st = TCLBM_OK;
+  hipError_t e = hipEventRecord(e0, c->stream);
+  if (e == hipSuccess) {
+    st = do_steps(c, nsteps);
+    e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+    *ms = f;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != TCLBM_OK) return st;
+  if (e != hipSuccess) {
+    set_err(c, "timing: %s", hipGetErrorString(e));
+    return TCLBM_E_DEVICE;
+  }
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_moments(tclbm_handle c, double *rho, double *ux, double *uy, double *T, tclbm_sums *sums) {
+  if (!c) return TCLBM_E_INVALID;
+  if (!bc_pairs_ok(c->k)) return TCLBM_E_INVALID;
+  const long long n = (long long)c->p.nx * c->p.ny;
+  const bool want = rho || ux || uy || T;
+  if (want && !c->fields) {
+    hipError_t e = hipMalloc(&c->fields, sizeof(double) * 4 * (size_t)n);
+    if (e != hipSuccess) {
+      c->fields = nullptr;
+      set_err(c, "hipMalloc fields: %s", hipGetErrorString(e));
+      return TCLBM_E_NOMEM;
+    }
+  }
+  double *F = c->fields;
+  KParams k = c->k;
+  k.src = c->buf[c->cur];
+  int nb = 0;
+  HIP_TRY(c, launch_moments(k, c->p.storage, want ? F : nullptr, want ? F + n : nullptr,
+                            want ? F + 2 * n : nullptr, want ? F + 3 * n : nullptr, c->partials, &nb, c->stream));
+  std::vector<double> part((size_t)nb * kNumSums);
+  HIP_TRY(c, hipMemcpyAsync(part.data(), c->partials, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  double *outs[4] = {rho, ux, uy, T};
+  for (int q = 0; q < 4; ++q)
+    if (outs[q])
+      HIP_TRY(c, hipMemcpyAsync(outs[q], F + (size_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  tclbm_sums s;
+  memset(&s, 0, sizeof(s));
+  s.rho_min = 1e300;
+  s.T_min = 1e300;
+  double bad = 0;
+  for (int b = 0; b < nb; ++b) {  // fixed order: deterministic
+    const double *v = &part[(size_t)b * kNumSums];
+    s.mass += v[kSumMass];
+    s.momx += v[kSumMx];
+    s.momy += v[kSumMy];
+    s.energy += v[kSumE];
+    s.kinetic += v[kSumKin];
+    s.nu_num += v[kSumNu];
+    s.rho_min = std::fmin(s.rho_min, v[kSumRhoMin]);
+    s.T_min = std::fmin(s.T_min, v[kSumTMin]);
+    bad += v[kSumBad];
+  }
+  s.nonfinite = (int64_t)bad;
+  if (sums) *sums = s;
+  if (s.nonfinite > 0 || !(s.rho_min > 0) || !(s.T_min > 0)) {
+    c->unstable = true;
+    set_err(c, "unstable state: %lld non-finite nodes, rho_min %g, T_min %g", (long long)s.nonfinite, s.rho_min,
+            s.T_min);
+    return TCLBM_E_UNSTABLE;
+  }
+  return TCLBM_OK;
+}
+
+int64_t tclbm_steps_done(tclbm_handle c) { return c ? c->steps : -1; }
+
+tclbm_status tclbm_read_state(tclbm_handle c, double *out) {
+  if (!c || !out) return TCLBM_E_INVALID;
+  const size_t cnt = (size_t)c->p.nx * c->p.ny * (c->p.thermal ? 18 : 9);
+  double *d = nullptr;
+  hipError_t e = hipMalloc(&d, cnt * sizeof(double));
+  if (e != hipSuccess) {
+    set_err(c, "hipMalloc: %s", hipGetErrorString(e));
+    return TCLBM_E_NOMEM;
+  }
+  KParams k = c->k;
+  k.src = c->buf[c->cur];
+  e = launch_read_state(k, c->p.storage, d, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(d);
+  if (e != hipSuccess) {
+    set_err(c, "read_state: %s", hipGetErrorString(e));
+    return TCLBM_E_DEVICE;
+  }
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_destroy(tclbm_handle c) {
+  if (!c) return TCLBM_E_INVALID;
+  hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->fields) hipFree(c->fields);
+  delete c;
+  return TCLBM_OK;
+}
+
+const char *tclbm_status_str(tclbm_status s) {
+  switch (s) {
+    case TCLBM_OK: return "ok";
+    case TCLBM_E_INVALID: return "invalid argument";
+    case TCLBM_E_NOMEM: return "out of memory";
+    case TCLBM_E_DEVICE: return "device error";
+    case TCLBM_E_STATE: return "handle unusable";
+    case TCLBM_E_UNSTABLE: return "unstable state";
+    default: return "unknown status";
+  }
+}
+
+const char *tclbm_last_error(tclbm_handle c) { return c ? c->err : "no handle"; }
+
+tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
+  if (!dst || !src || (bytes & 15) || (reinterpret_cast<uintptr_t>(dst) & 15) ||
+      (reinterpret_cast<uintptr_t>(src) & 15))
+    return TCLBM_E_INVALID;
+  hipError_t e = launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? TCLBM_OK : TCLBM_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// tclbm_internal.h -- declarations shared by the HIP kernels and the C-ABI host
+// code of libtclbm (not installed; the public interface is include/tclbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tclbm {
+
+enum StoreKind { kF32 = 0, kF16 = 1, kBF16 = 2, kF64 = 3 };
+enum BcKind { kPeriodic = 0, kBounceBack = 1, kWall = 2 };
+enum Side { kXlo = 0, kXhi = 1, kYlo = 2, kYhi = 3 };
+
+// Everything a kernel needs, passed by value.  Physical constants are double
+// here and converted to the kernel's arithmetic type on entry.
+struct KParams {
+  const void *src;  // population buffer read this step (storage type)
+  void *dst;        // population buffer written this step
+  int nx, ny;
+  int pitch;        // elements per stored row (>= nx)
+  long long plane;  // elements per population plane (pitch * ny)
+  int thermal, correction, heq_mode, h_coll, wall_rho;
+  int bc[4];
+  double wall_ux[4], wall_uy[4], wall_T[4];
+  double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;
+  const void *axf, *ayf;          // per-node acceleration, compute type, pitch layout (nullable)
+  const float *refF, *refH;       // per-row reference populations [ny][9] (16-bit storage)
+  // march decomposition
+  int tile_w, lane_off, n_xtiles, strip_rows, n_strips;
+};
+
+// Reduction record written per block by the moments kernel.
+enum { kSumMass = 0, kSumMx, kSumMy, kSumE, kSumKin, kSumNu, kSumRhoMin, kSumTMin, kSumBad, kNumSums };
+
+size_t store_bytes(int storage);
+
+hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
+int step_waves_per_block();
+hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
+                       const double *d_uy, const double *d_T, hipStream_t s);
+// fields (device, double, nx*ny each, nullable) and per-block partial sums
+hipError_t launch_moments(const KParams &k, int storage, double *d_rho, double *d_ux, double *d_uy,
+                          double *d_T, double *d_partials, int *nblocks_out, hipStream_t s);
+int moments_blocks(const KParams &k);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipStream_t s);
+
+}  // namespace tclbm

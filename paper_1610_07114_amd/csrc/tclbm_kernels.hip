@@ -1,0 +1,640 @@
+// tclbm_kernels.hip -- gfx950 kernels of the thermal cascaded LBM step.
+//
+// Data layout (per population buffer): 9 planes of f then 9 planes of h
+// (h omitted when athermal), each plane ny rows of `pitch` elements, x fastest.
+// A buffer holds post-collision populations at their own node; the next step
+// pulls them (f_a(x, t+1) = P_a(x - e_a, t)), so one step reads 18 and writes
+// 18 values per node: one HBM pass.
+//
+// Step kernel decomposition: one wave64 owns a tile of tile_w consecutive
+// columns (plus one halo column on each side, two on the left when x is not
+// periodic) and marches upwards through a strip of strip_rows rows.  Each lane
+// keeps the pulled populations of the current row in registers together with
+// u(1 - theta) of the rows below; the x-derivative of the correction term comes
+// from neighbouring lanes through wave shuffles, the y-derivative from the
+// register window, so every node's macroscopic values are computed once per
+// row visit and the halo costs 2/64 lanes plus two rows per strip.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "tclbm_internal.h"
+#include "tclbm_node.h"
+
+namespace tclbm {
+
+namespace {
+
+// D2Q9 order of Section 2: 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// ---------------------------------------------------------------- storage ---
+template <int S>
+struct Store;
+template <>
+struct Store<kF32> {
+  using T = float;
+  static __device__ __forceinline__ float ld(const T *p, long long i, float) { return p[i]; }
+  static __device__ __forceinline__ void st(T *p, long long i, float v, float) { p[i] = v; }
+};
+template <>
+struct Store<kF64> {
+  using T = double;
+  static __device__ __forceinline__ double ld(const T *p, long long i, double) { return p[i]; }
+  static __device__ __forceinline__ void st(T *p, long long i, double v, double) { p[i] = v; }
+};
+template <>
+struct Store<kF16> {  // deviation from the row reference, IEEE half, RNE
+  using T = unsigned short;
+  static __device__ __forceinline__ float ld(const T *p, long long i, float ref) {
+    return ref + __half2float(__ushort_as_half(p[i]));
+  }
+  static __device__ __forceinline__ void st(T *p, long long i, float v, float ref) {
+    p[i] = __half_as_ushort(__float2half_rn(v - ref));
+  }
+};
+template <>
+struct Store<kBF16> {  // deviation from the row reference, bfloat16, RNE
+  using T = unsigned short;
+  static __device__ __forceinline__ float ld(const T *p, long long i, float ref) {
+    return ref + __bfloat162float(__ushort_as_bfloat16(p[i]));
+  }
+  static __device__ __forceinline__ void st(T *p, long long i, float v, float ref) {
+    p[i] = __bfloat16_as_ushort(__float2bfloat16(v - ref));
+  }
+};
+
+template <int S>
+struct Real {
+  using T = float;
+};
+template <>
+struct Real<kF64> {
+  using T = double;
+};
+
+template <int S>
+constexpr bool kDev = (S == kF16 || S == kBF16);
+
+// ------------------------------------------------------------- utilities ---
+template <class R>
+__device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
+  Consts<R> c;
+  c.R_ = (R)k.R;
+  c.T0 = (R)k.T0;
+  c.b = (R)k.b;
+  c.w1 = (R)k.w1;
+  c.w2 = (R)k.w2;
+  c.w3 = (R)k.w3;
+  c.w4 = (R)k.w4;
+  c.wh = (R)k.wh;
+  c.inv_tau_hf = (R)k.inv_tau_hf;
+  c.inv_bR2 = (R)(2.0 / (k.b * k.R));
+  c.thermal = k.thermal;
+  c.correction = k.correction;
+  c.heq_mode = k.heq_mode;
+  c.h_coll = k.h_coll;
+  return c;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; renumber them so that each XCD
+// receives one contiguous range of logical blocks (neighbouring tiles share
+// their halo lines in that XCD's L2).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int nx = 8;
+  int q = nb / nx, r = nb - q * nx;
+  int x = b % nx, i = b / nx;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Column bookkeeping of one lane.
+struct Col {
+  int xc;         // column whose node this lane evaluates
+  int xm, xp;     // source columns of links with e_x = +1 / -1
+  bool outL, outR;  // those links come from outside (non-periodic x)
+};
+
+__device__ __forceinline__ Col make_col(const KParams &k, int xl) {
+  Col c;
+  if (k.bc[kXlo] == kPeriodic) {
+    int x = xl % k.nx;
+    if (x < 0) x += k.nx;
+    c.xc = x;
+    c.xm = (x == 0) ? k.nx - 1 : x - 1;
+    c.xp = (x == k.nx - 1) ? 0 : x + 1;
+    c.outL = false;
+    c.outR = false;
+  } else {
+    int x = xl < 0 ? 0 : (xl >= k.nx ? k.nx - 1 : xl);
+    c.xc = x;
+    c.outL = (x == 0);
+    c.outR = (x == k.nx - 1);
+    c.xm = c.outL ? x : x - 1;
+    c.xp = c.outR ? x : x + 1;
+  }
+  return c;
+}
+
+template <class R>
+__device__ __forceinline__ void node_accel(const KParams &k, int y, int x, R &ax, R &ay) {
+  if (k.axf) {
+    long long i = (long long)y * k.pitch + x;
+    ax = reinterpret_cast<const R *>(k.axf)[i];
+    ay = reinterpret_cast<const R *>(k.ayf)[i];
+  } else {
+    ax = (R)k.ax;
+    ay = (R)k.ay;
+  }
+}
+
+// Pull the populations that arrive at (col.xc, y): f_a = P_a(x - e_a).  Links
+// from outside a non-periodic side bounce back halfway at rest:
+// f_a = P_opp(a)(x) (for WALL rows those values are never used).
+template <int S>
+__device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
+                                     typename Real<S>::T *f, typename Real<S>::T *h) {
+  using ST = typename Store<S>::T;
+  const ST *src = reinterpret_cast<const ST *>(k.src);
+  int ym, yp;
+  bool outB, outT;
+  if (k.bc[kYlo] == kPeriodic) {
+    ym = (y == 0) ? k.ny - 1 : y - 1;
+    yp = (y == k.ny - 1) ? 0 : y + 1;
+    outB = outT = false;
+  } else {
+    outB = (y == 0);
+    outT = (y == k.ny - 1);
+    ym = outB ? y : y - 1;
+    yp = outT ? y : y + 1;
+  }
+  const long long own = (long long)y * k.pitch + col.xc;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+    const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
+    const int sy = kEy[a] > 0 ? ym : (kEy[a] < 0 ? yp : y);
+    const bool oy = kEy[a] > 0 ? outB : (kEy[a] < 0 ? outT : false);
+    const bool bb = ox || oy;
+    const int pa = bb ? kOpp[a] : a;
+    const int ry = bb ? y : sy;
+    const long long idx = (long long)pa * k.plane + (bb ? own : (long long)sy * k.pitch + sx);
+    float rf = 0.f, rh = 0.f;
+    if (kDev<S>) {
+      rf = k.refF[ry * 9 + pa];
+      rh = k.refH[ry * 9 + pa];
+    }
+    f[a] = Store<S>::ld(src, idx, rf);
+    if (k.thermal) h[a] = Store<S>::ld(src, idx + 9 * k.plane, rh);
+  }
+}
+
+// Populations of a WALL row node by non-equilibrium extrapolation from the
+// adjacent fluid node (fI, hI, mI):
+// X(x_b) = X^eq(rho_w, u_w, T_w) + [X(x_f) - X^eq(rho_f, u_f, T_f)].
+// fw holds on entry the populations pulled at the wall node; those that came
+// from the fluid and the tangential ones fix rho_w (default reading).
+template <class R>
+__device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const R *fI, const R *hI,
+                                          const Macro<R> &mI, R aI_n, R aW_n, R *fw, R *hw) {
+  const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
+  const R Tw = k.thermal ? (R)k.wall_T[side] : c.T0;
+  R rw;
+  if (k.wall_rho == 1) {
+    rw = mI.rho;
+  } else if (k.wall_rho == 2) {
+    rw = (mI.rho * c.R_ * mI.T + mI.rho * aI_n) / (c.R_ * Tw);
+  } else {
+    // bottom: links from the fluid are e_y = -1 (4, 7, 8); top: e_y = +1 (2, 5, 6)
+    R k0 = fw[0] + fw[1] + fw[3];
+    R kin = (side == kYlo) ? (fw[4] + fw[7] + fw[8]) : (fw[2] + fw[5] + fw[6]);
+    R un = (side == kYlo) ? -uwy : uwy;
+    rw = (k0 + R(2) * kin) / (R(1) + un - R(0.5) * aW_n);
+  }
+  R ew[9], ef[9];
+  feq9(rw, uwx, uwy, c.R_ * Tw, ew);
+  feq9(mI.rho, mI.ux, mI.uy, c.R_ * mI.T, ef);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) fw[a] = ew[a] + (fI[a] - ef[a]);
+  if (k.thermal) {
+    heq9(rw, uwx, uwy, c.R_ * Tw, c.b, c.heq_mode, ew);
+    heq9(mI.rho, mI.ux, mI.uy, c.R_ * mI.T, c.b, c.heq_mode, ef);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) hw[a] = ew[a] + (hI[a] - ef[a]);
+  }
+}
+
+template <class R>
+struct RowState {
+  R f[9], h[9];
+  Macro<R> m;
+  R qx, qy;  // u (1 - theta)
+};
+
+template <class R>
+__device__ __forceinline__ void finish(const KParams &k, const Consts<R> &c, int y, int xc, RowState<R> &s) {
+  R ax, ay;
+  node_accel<R>(k, y, xc, ax, ay);
+  s.m = macros(c, s.f, s.h, ax, ay);
+  R om = R(1) - s.m.T / c.T0;
+  s.qx = s.m.ux * om;
+  s.qy = s.m.uy * om;
+}
+
+__device__ __forceinline__ bool is_wall_row(const KParams &k, int y) {
+  return (y == 0 && k.bc[kYlo] == kWall) || (y == k.ny - 1 && k.bc[kYhi] == kWall);
+}
+
+// State of row y (not a WALL row): pull and evaluate.
+template <int S>
+__device__ __forceinline__ void get_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
+                                        const Col &col, RowState<typename Real<S>::T> &s) {
+  pull<S>(k, y, col, s.f, s.h);
+  finish(k, c, y, col.xc, s);
+}
+
+// State of the WALL row y whose fluid neighbour state is `in`.
+template <int S>
+__device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
+                                             const Col &col, const RowState<typename Real<S>::T> &in,
+                                             RowState<typename Real<S>::T> &s) {
+  using R = typename Real<S>::T;
+  const int side = (y == 0) ? kYlo : kYhi;
+  const int yf = (y == 0) ? 1 : y - 1;
+  if (k.wall_rho == 0) pull<S>(k, y, col, s.f, s.h);
+  R axI, ayI, axW, ayW;
+  node_accel<R>(k, yf, col.xc, axI, ayI);
+  node_accel<R>(k, y, col.xc, axW, ayW);
+  const R aI_n = (side == kYlo) ? -ayI : ayI;
+  const R aW_n = (side == kYlo) ? -ayW : ayW;
+  wall_node<R>(k, c, side, in.f, in.h, in.m, aI_n, aW_n, s.f, s.h);
+  finish(k, c, y, col.xc, s);
+}
+
+template <class R>
+__device__ __forceinline__ R shfl_dn(R v, int d) {
+  return __shfl_down(v, d, 64);
+}
+template <class R>
+__device__ __forceinline__ R shfl_up(R v, int d) {
+  return __shfl_up(v, d, 64);
+}
+
+// d/dx[u_x (1 - theta)] at this lane's node: central difference with the
+// neighbouring lanes, one-sided second order on a non-periodic edge.  Every
+// lane of the wave must call it (shuffles).
+template <class R>
+__device__ __forceinline__ R ddx(const KParams &k, R q, int xl) {
+  R qp = shfl_dn(q, 1), qm = shfl_up(q, 1);
+  if (k.bc[kXlo] == kPeriodic) return R(0.5) * (qp - qm);
+  R qpp = shfl_dn(q, 2), qmm = shfl_up(q, 2);
+  if (xl == 0) return R(0.5) * (R(-3) * q + R(4) * qp - qpp);
+  if (xl == k.nx - 1) return R(0.5) * (R(3) * q - R(4) * qm + qmm);
+  return R(0.5) * (qp - qm);
+}
+
+// Collide the current row and store it.
+template <int S>
+__device__ __forceinline__ void collide_store(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
+                                              const Col &col, bool store, const RowState<typename Real<S>::T> &s,
+                                              typename Real<S>::T Dy, int xl) {
+  using R = typename Real<S>::T;
+  using ST = typename Store<S>::T;
+  const R Dx = ddx<R>(k, s.qx, xl);
+  R ax, ay;
+  node_accel<R>(k, y, col.xc, ax, ay);
+  R P[9], Q[9];
+  collide(c, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
+  if (!store) return;
+  ST *dst = reinterpret_cast<ST *>(k.dst);
+  const long long own = (long long)y * k.pitch + col.xc;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    float rf = 0.f, rh = 0.f;
+    if (kDev<S>) {
+      rf = k.refF[y * 9 + a];
+      rh = k.refH[y * 9 + a];
+    }
+    Store<S>::st(dst, (long long)a * k.plane + own, P[a], rf);
+    if (k.thermal) Store<S>::st(dst, (long long)(a + 9) * k.plane + own, Q[a], rh);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ step kernel ---
+constexpr int kStepWaves = 4;
+
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
+  using R = typename Real<S>::T;
+  const int lane = threadIdx.x & 63;
+  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
+  const int strip = wave / k.n_xtiles;
+  const int xt = wave - strip * k.n_xtiles;
+  const int r0 = strip * k.strip_rows;
+  const int r1 = min(r0 + k.strip_rows, k.ny);
+  const int xl = xt * k.tile_w - k.lane_off + lane;
+  const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
+  const Col col = make_col(k, xl);
+  const Consts<R> c = make_consts<R>(k);
+  const bool yper = (k.bc[kYlo] == kPeriodic);
+  const int ny = k.ny;
+
+  RowState<R> cur, nxt;
+  R qy_m1 = R(0), qy_m2 = R(0);
+  int j;
+  if (!yper && r0 == 0) {
+    // bottom edge: row 0 needs u(1-theta) of rows 1 and 2 (one-sided difference)
+    get_row<S>(k, c, 1, col, nxt);                       // row 1 (ny >= 3: a fluid row)
+    RowState<R> two;
+    if (is_wall_row(k, 2)) get_wall_row<S>(k, c, 2, col, nxt, two);
+    else get_row<S>(k, c, 2, col, two);
+    if (is_wall_row(k, 0)) get_wall_row<S>(k, c, 0, col, nxt, cur);
+    else get_row<S>(k, c, 0, col, cur);
+    const R Dy = R(0.5) * (R(-3) * cur.qy + R(4) * nxt.qy - two.qy);
+    collide_store<S>(k, c, 0, col, store, cur, Dy, xl);
+    qy_m1 = cur.qy;
+    cur = nxt;
+    j = 1;
+  } else {
+    const int ya = yper ? (r0 == 0 ? ny - 1 : r0 - 1) : r0 - 1;  // row below the strip
+    if (!yper && ya == 0 && is_wall_row(k, 0)) {
+      get_row<S>(k, c, r0, col, cur);
+      get_wall_row<S>(k, c, 0, col, cur, nxt);
+      qy_m1 = nxt.qy;
+    } else {
+      get_row<S>(k, c, ya, col, nxt);
+      qy_m1 = nxt.qy;
+      if (!yper && r1 == ny && r0 >= 2) {
+        // strip holds the top edge: also u(1-theta) two rows below its start
+        RowState<R> low;
+        if (r0 - 2 == 0 && is_wall_row(k, 0)) get_wall_row<S>(k, c, 0, col, nxt, low);
+        else get_row<S>(k, c, r0 - 2, col, low);
+        qy_m2 = low.qy;
+      }
+      if (is_wall_row(k, r0)) get_wall_row<S>(k, c, r0, col, nxt, cur);
+      else get_row<S>(k, c, r0, col, cur);
+    }
+    j = r0;
+  }
+
+  for (; j < r1; ++j) {
+    if (!yper && j == ny - 1) {  // top edge: one-sided difference with the rows below
+      const R Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_m1 + qy_m2);
+      collide_store<S>(k, c, j, col, store, cur, Dy, xl);
+      break;
+    }
+    const int yn = (j == ny - 1) ? 0 : j + 1;
+    if (!yper && is_wall_row(k, yn)) get_wall_row<S>(k, c, yn, col, cur, nxt);
+    else get_row<S>(k, c, yn, col, nxt);
+    const R Dy = R(0.5) * (nxt.qy - qy_m1);
+    collide_store<S>(k, c, j, col, store, cur, Dy, xl);
+    qy_m2 = qy_m1;
+    qy_m1 = cur.qy;
+    cur = nxt;
+  }
+}
+
+int step_waves_per_block() { return kStepWaves; }
+
+hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
+  const int waves = k.n_xtiles * k.n_strips;
+  const int blocks = (waves + kStepWaves - 1) / kStepWaves;
+  dim3 grid(blocks), block(64 * kStepWaves);
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(step_kernel<kF32>, grid, block, 0, s, k); break;
+    case kF16: hipLaunchKernelGGL(step_kernel<kF16>, grid, block, 0, s, k); break;
+    case kBF16: hipLaunchKernelGGL(step_kernel<kBF16>, grid, block, 0, s, k); break;
+    case kF64: hipLaunchKernelGGL(step_kernel<kF64>, grid, block, 0, s, k); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t store_bytes(int storage) {
+  switch (storage) {
+    case kF32: return 4;
+    case kF16:
+    case kBF16: return 2;
+    case kF64: return 8;
+    default: return 0;
+  }
+}
+
+// ------------------------------------------------------------ init kernel ---
+// P_a(x) = fbar^init_a(x + e_a) so that the first pull returns the initial
+// state; a link leaving through a bounce-back side stores the opposite
+// population of the same node (the value that bounces back into it).
+template <int S>
+__global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho, const double *ux,
+                                                   const double *uy, const double *T) {
+  using R = typename Real<S>::T;
+  using ST = typename Store<S>::T;
+  const long long n = (long long)k.nx * k.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int y = (int)(i / k.nx), x = (int)(i - (long long)y * k.nx);
+  const Consts<R> c = make_consts<R>(k);
+  const bool xper = k.bc[kXlo] == kPeriodic, yper = k.bc[kYlo] == kPeriodic;
+  ST *dst = reinterpret_cast<ST *>(k.dst);
+  const long long own = (long long)y * k.pitch + x;
+#pragma unroll 1
+  for (int a = 0; a < 9; ++a) {
+    int tx = x + kEx[a], ty = y + kEy[a];
+    bool out = false;
+    if (xper) tx = (tx + k.nx) % k.nx;
+    else if (tx < 0 || tx >= k.nx) out = true;
+    if (yper) ty = (ty + k.ny) % k.ny;
+    else if (ty < 0 || ty >= k.ny) out = true;
+    int comp = a;
+    if (out) {  // bounce-back (or wall row: value unused)
+      tx = x;
+      ty = y;
+      comp = kOpp[a];
+    }
+    const long long j = (long long)ty * k.nx + tx;
+    const R r = (R)rho[j], vx = (R)ux[j], vy = (R)uy[j];
+    const R t = k.thermal ? (R)T[j] : c.T0;
+    R ax, ay;
+    node_accel<R>(k, ty, tx, ax, ay);
+    R fe[9], se[9], he[9];
+    feq9(r, vx, vy, c.R_ * t, fe);
+    source9(r, vx, vy, ax, ay, se);
+    float rf = 0.f, rh = 0.f;
+    if (kDev<S>) {
+      rf = k.refF[y * 9 + a];
+      rh = k.refH[y * 9 + a];
+    }
+    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp], rf);
+    if (k.thermal) {
+      heq9(r, vx, vy, c.R_ * t, c.b, c.heq_mode, he);
+      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp], rh);
+    }
+  }
+}
+
+hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
+                       const double *d_uy, const double *d_T, hipStream_t s) {
+  const long long n = (long long)k.nx * k.ny;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(init_kernel<kF32>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T); break;
+    case kF16: hipLaunchKernelGGL(init_kernel<kF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T); break;
+    case kBF16: hipLaunchKernelGGL(init_kernel<kBF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T); break;
+    case kF64: hipLaunchKernelGGL(init_kernel<kF64>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- moments kernel ---
+// Macroscopic fields of the state the next step sees (WALL rows after their
+// extrapolation) and FP64 block sums (fixed-order tree in LDS, so repeated
+// calls give bitwise-identical sums).
+constexpr int kMomThreads = 256;
+
+template <int S>
+__global__ __launch_bounds__(kMomThreads) void moments_kernel(KParams k, double *frho, double *fux, double *fuy,
+                                                              double *fT, double *partials) {
+  using R = typename Real<S>::T;
+  __shared__ double red[kNumSums][kMomThreads];
+  const long long n = (long long)k.nx * k.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const Consts<R> c = make_consts<R>(k);
+  double v[kNumSums];
+#pragma unroll
+  for (int q = 0; q < kNumSums; ++q) v[q] = 0.0;
+  v[kSumRhoMin] = 1e300;
+  v[kSumTMin] = 1e300;
+  if (i < n) {
+    const int y = (int)(i / k.nx), x = (int)(i - (long long)y * k.nx);
+    const Col col = make_col(k, x);
+    RowState<R> s;
+    if (is_wall_row(k, y)) {
+      RowState<R> in;
+      get_row<S>(k, c, (y == 0) ? 1 : y - 1, col, in);
+      get_wall_row<S>(k, c, y, col, in, s);
+    } else {
+      get_row<S>(k, c, y, col, s);
+    }
+    const double r = (double)s.m.rho, u = (double)s.m.ux, w = (double)s.m.uy, t = (double)s.m.T;
+    if (frho) frho[i] = r;
+    if (fux) fux[i] = u;
+    if (fuy) fuy[i] = w;
+    if (fT) fT[i] = t;
+    double hs = 0.0;
+    if (k.thermal)
+      for (int a = 0; a < 9; ++a) hs += (double)s.h[a];
+    const bool bad = !(isfinite(r) && isfinite(u) && isfinite(w) && isfinite(t));
+    v[kSumMass] = r;
+    v[kSumMx] = r * u;
+    v[kSumMy] = r * w;
+    v[kSumE] = hs;
+    v[kSumKin] = 0.5 * r * (u * u + w * w);
+    v[kSumNu] = w * (t - k.T0);
+    v[kSumRhoMin] = bad ? -1.0 : r;
+    v[kSumTMin] = bad ? -1.0 : t;
+    v[kSumBad] = bad ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kNumSums; ++q) red[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int st = kMomThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+#pragma unroll
+      for (int q = 0; q < kNumSums; ++q) {
+        double o = red[q][threadIdx.x + st];
+        if (q == kSumRhoMin || q == kSumTMin) red[q][threadIdx.x] = fmin(red[q][threadIdx.x], o);
+        else red[q][threadIdx.x] += o;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kNumSums; ++q) partials[(long long)blockIdx.x * kNumSums + q] = red[q][0];
+  }
+}
+
+int moments_blocks(const KParams &k) {
+  const long long n = (long long)k.nx * k.ny;
+  return (int)((n + kMomThreads - 1) / kMomThreads);
+}
+
+hipError_t launch_moments(const KParams &k, int storage, double *d_rho, double *d_ux, double *d_uy, double *d_T,
+                          double *d_partials, int *nblocks_out, hipStream_t s) {
+  const int nb = moments_blocks(k);
+  if (nblocks_out) *nblocks_out = nb;
+  dim3 grid(nb), block(kMomThreads);
+  switch (storage) {
+    case kF32:
+      hipLaunchKernelGGL(moments_kernel<kF32>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      break;
+    case kF16:
+      hipLaunchKernelGGL(moments_kernel<kF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(moments_kernel<kBF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      break;
+    case kF64:
+      hipLaunchKernelGGL(moments_kernel<kF64>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------- raw state readback ---
+template <int S>
+__global__ __launch_bounds__(256) void read_state_kernel(KParams k, double *out) {
+  using ST = typename Store<S>::T;
+  const long long n = (long long)k.nx * k.ny;
+  const int np = k.thermal ? 18 : 9;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * np) return;
+  const int a = (int)(i / n);
+  const long long node = i - (long long)a * n;
+  const int y = (int)(node / k.nx), x = (int)(node - (long long)y * k.nx);
+  const ST *src = reinterpret_cast<const ST *>(k.src);
+  float ref = 0.f;
+  if (kDev<S>) ref = (a < 9) ? k.refF[y * 9 + a] : k.refH[y * 9 + (a - 9)];
+  out[i] = (double)Store<S>::ld(src, (long long)a * k.plane + (long long)y * k.pitch + x, ref);
+}
+
+hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipStream_t s) {
+  const long long n = (long long)k.nx * k.ny * (k.thermal ? 18 : 9);
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(read_state_kernel<kF32>, grid, block, 0, s, k, d_out); break;
+    case kF16: hipLaunchKernelGGL(read_state_kernel<kF16>, grid, block, 0, s, k, d_out); break;
+    case kBF16: hipLaunchKernelGGL(read_state_kernel<kBF16>, grid, block, 0, s, k, d_out); break;
+    case kF64: hipLaunchKernelGGL(read_state_kernel<kF64>, grid, block, 0, s, k, d_out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------- HBM copy probe ---
+// Plain streaming copy (16-byte vectors, grid-stride) used to measure the
+// achievable HBM bandwidth and to calibrate byte counters.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   long long n16) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  const long long n16 = (long long)(bytes / 16);
+  if (n16 <= 0) return hipSuccess;
+  long long blocks = (n16 + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src),
+                     reinterpret_cast<uint4 *>(dst), n16);
+  return hipGetLastError();
+}
+
+}  // namespace tclbm

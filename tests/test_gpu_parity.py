@@ -1,0 +1,205 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs.  Tolerances: FP32 fields within 1e-5 relative L-inf after
+100 steps (rho and T relative to their max, u relative to max |u| of the
+oracle); the FP64 instantiation within 1e-10; 16-bit storage within the bounds
+stated per test.  Sizes span several tiles and strips with ragged tails."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import oracle_lattice
+from paper_1610_07114_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_07114_amd import tclbm
+    return tclbm
+
+
+def rel_err(gpu, ora):
+    r, u, v, t = gpu
+    r0, u0, v0, t0 = ora
+    us = max(np.abs(u0).max(), np.abs(v0).max(), 1e-300)
+    return dict(rho=np.abs(r - r0).max() / np.abs(r0).max(), T=np.abs(t - t0).max() / np.abs(t0).max(),
+                ux=np.abs(u - u0).max() / us, uy=np.abs(v - v0).max() / us)
+
+
+def run_pair(T, case, steps, storage="f32", gpu_over=None, orc_over=None, tuning=None):
+    gpu_over = gpu_over or {}
+    orc_over = orc_over or {}
+    lat = T.Lattice(case, storage=storage, **gpu_over)
+    if tuning:
+        lat.set_tuning(*tuning)
+    lat.step(steps)
+    r, u, v, t, s = lat.moments()
+    lat.close()
+    ora = oracle_lattice(case, **orc_over).step(steps).macros()
+    return (r, u, v, t), ora, s
+
+
+def test_periodic_thermal_fp32(T):
+    case = W.uniform_noise(200, 37, seed=1, ax=3e-5, ay=-2e-5, pointwise=2e-3)
+    say(f"case periodic thermal fp32 {case.nx}x{case.ny} 100 steps")
+    g, o, _ = run_pair(T, case, 100, tuning=(5, 32))
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+
+
+def test_periodic_thermal_fp64(T):
+    case = W.uniform_noise(200, 37, seed=2, ax=3e-5, ay=-2e-5, pointwise=2e-3)
+    say(f"case periodic thermal fp64 {case.nx}x{case.ny} 100 steps")
+    g, o, _ = run_pair(T, case, 100, storage="f64", tuning=(6, 32))
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+
+
+def test_decomposition_and_graphs_are_bitwise_neutral(T):
+    case = W.uniform_noise(131, 29, seed=3, ax=1e-5, pointwise=2e-3)
+    say("case decomposition neutrality 131x29 fp32, 70 steps")
+    states = []
+    for tuning in [(0, 0), (3, 0), (7, 4), (29, 32)]:
+        lat = T.Lattice(case, storage="f32")
+        lat.set_tuning(*tuning)
+        lat.step(70)
+        states.append(lat.read_state())
+        lat.close()
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
+
+
+def test_couette_fp64_20000_steps(T):
+    case = W.couette()
+    say("case couette 8x32 fp64 20000 steps")
+    g, o, _ = run_pair(T, case, case.steps, storage="f64")
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+    ua, Ta = W.couette_closed_form(case)
+    heating = Ta - (1.0 + 0.02 * np.arange(case.ny) / case.meta["H"])
+    assert np.abs(g[3] - Ta[:, None]).max() < 0.01 * heating.max()
+
+
+def test_couette_fp32(T):
+    case = W.couette()
+    say("case couette 8x32 fp32 100 steps")
+    g, o, _ = run_pair(T, case, 100)
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+
+
+def test_rb_fp32_100_steps(T):
+    case = W.rayleigh_benard(nx=512, ny=256, seed=0)
+    say("case rayleigh-benard 512x256 fp32 100 steps")
+    g, o, _ = run_pair(T, case, 100)
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+
+
+def test_rb_fp64_small(T):
+    case = W.rayleigh_benard(nx=130, ny=67, seed=4, noise=1e-3)
+    say("case rayleigh-benard 130x67 fp64 300 steps")
+    g, o, _ = run_pair(T, case, 300, storage="f64", tuning=(9, 32))
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+
+
+def test_shock_tube_fp32(T):
+    case = W.shock_tube()
+    say("case shock tube 8192x4 fp32 100 steps")
+    g, o, _ = run_pair(T, case, 100)
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+
+
+def test_shock_tube_fp64_bounce_back(T):
+    case = W.shock_tube(nx=700, ny=5, steps=400)
+    say("case shock tube 700x5 fp64 400 steps")
+    g, o, _ = run_pair(T, case, 400, storage="f64")
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+
+
+def test_bounce_back_box_fp64(T):
+    case = W.uniform_noise(70, 45, seed=6, ay=-1e-4, pointwise=1e-3).with_(
+        bc=(W.BOUNCEBACK, W.BOUNCEBACK, W.BOUNCEBACK, W.BOUNCEBACK))
+    say("case closed bounce-back box 70x45 fp64 150 steps")
+    g, o, _ = run_pair(T, case, 150, storage="f64")
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+
+
+def test_athermal_force_field_fp64(T):
+    case = W.taylor_green(N=64, u0=0.05)
+    say("case taylor-green athermal 64x64 fp64 500 steps (per-node force)")
+    g, o, _ = run_pair(T, case, 500, storage="f64")
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e["rho"], e["ux"], e["uy"]) < 1e-10
+
+
+@pytest.mark.parametrize("opts", [dict(heq_moments=1, h_collision=1), dict(wall_rho=1), dict(wall_rho=2)])
+def test_reading_options_fp64(T, opts):
+    case = W.couette(u0=0.05)
+    say(f"case couette options {opts} fp64 2000 steps")
+    g, o, _ = run_pair(T, case, 2000, storage="f64", gpu_over=opts, orc_over=opts)
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-10
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_16bit_storage_parity(T, storage, tol):
+    case = W.rayleigh_benard(nx=256, ny=128, seed=0, noise=1e-3)
+    say(f"case rayleigh-benard 256x128 {storage} storage 100 steps")
+    g, o, _ = run_pair(T, case, 100, storage=storage)
+    e = rel_err(g, o)
+    say(f"  errors {e}")
+    assert max(e["rho"], e["T"]) < tol
+
+
+def test_conservation_sums_fp64(T):
+    case = W.uniform_noise(96, 50, seed=9, ax=2e-5, ay=1e-5)
+    say("case periodic conservation fp64 96x50")
+    lat = T.Lattice(case, storage="f64")
+    _, _, _, _, s0 = lat.moments()
+    lat.step(64)
+    _, _, _, _, s1 = lat.moments()
+    lat.close()
+    assert s1.mass == pytest.approx(s0.mass, rel=1e-13)
+    assert s1.energy == pytest.approx(s0.energy, rel=1e-13)
+    assert s1.momx == pytest.approx(s0.momx + 64 * s0.mass * case.ax, rel=1e-10)
+    assert s1.momy == pytest.approx(s0.momy + 64 * s0.mass * case.ay, rel=1e-10)
+
+
+def test_instability_is_reported(T):
+    case = W.uniform_noise(64, 64, seed=1, amp_u=0.45, amp_T=0.6, tau_f=0.501, pointwise=0.2)
+    say("case deliberately unstable state 64x64 (NaN arithmetic only)")
+    lat = T.Lattice(case, storage="f32")
+    lat.step(400)
+    _, _, _, _, s, st = T.tclbm_moments(lat.h, case.nx, case.ny, True, check=False)
+    assert st == T.E_UNSTABLE
+    with pytest.raises(T.TclbmError) as ei:
+        lat.step(1)
+    assert ei.value.status == T.E_STATE
+    lat.close()
