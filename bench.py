@@ -73,6 +73,27 @@ def cpu_baseline(case, seconds_target: float = 12.0):
                       f"{dt:.1f} s"}
 
 
+def copy_probe(torch, tclbm, nbytes: int = 2 << 30, reps: int = 20):
+    """Achievable HBM bandwidth of a plain streaming copy (read + write bytes per
+    launch / launch time), the measured ceiling beside the 8 TB/s peak."""
+    dev = torch.device("cuda:0")
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    a.fill_(1)
+    s = torch.cuda.Stream(dev)
+    for _ in range(3):
+        tclbm.tclbm_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        tclbm.tclbm_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    return {"probe": "hbm_copy", "bytes_per_launch": 2 * nbytes, "avg_launch_us": round(ms * 1e3, 2),
+            "GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +105,8 @@ def main():
     ap.add_argument("--strip-rows", type=int, default=0)
     ap.add_argument("--graph-chunk", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time the plain HBM copy kernel (2 x 2 GiB) instead and exit")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="per-launch HBM traffic from rocprofv3 counters (if measured for this kernel)")
     args = ap.parse_args()
@@ -96,6 +119,10 @@ def main():
 
     import torch
     from paper_1610_07114_amd import tclbm
+
+    if args.copy_probe:
+        print(json.dumps(copy_probe(torch, tclbm)), flush=True)
+        return
 
     case, wname = workload_case(args.workload)
     dev = torch.device("cuda:0")

@@ -50,9 +50,10 @@ typedef enum {
 } tclbm_status;
 
 /* Storage of f and h in device memory.  Arithmetic is FP32 for the first
- * three and FP64 for the last.  The 16-bit forms store each population as its
- * deviation from a per-row rest-state equilibrium (computed at create time from
- * the row means of the initial density and temperature). */
+ * three and FP64 for the last.  Every form stores each population as its
+ * deviation from a per-row rest-state equilibrium (fixed at create time from
+ * the row means of the initial density and temperature), and the arithmetic
+ * runs on those deviations. */
 typedef enum {
   TCLBM_STORE_F32 = 0,
   TCLBM_STORE_F16_DEV = 1,
@@ -88,6 +89,9 @@ typedef struct {
                             other moments at 1; default), 1 BGK (Section 4) */
   int32_t accel_field;   /* 1: tclbm_create receives per-node acceleration
                             arrays (space for them is part of the state) */
+  int32_t bc[4];         /* tclbm_bc_kind per side (tclbm_side order); the
+                            initial state is built for these boundaries */
+  double wall_ux[4], wall_uy[4], wall_T[4];  /* WALL sides: imposed u and T */
 } tclbm_params;
 
 /* FP64 whole-lattice reductions of the state the next step would see
@@ -103,7 +107,8 @@ typedef struct {
 } tclbm_sums;
 
 /* Fill *p with defaults: R = 1/3, T0 = 1, gamma = 1.4, Pr = 0.71, tau_f = 0.8,
- * w2 = w3 = w4 = 1, no force, thermal with correction, FP32 storage. */
+ * w2 = w3 = w4 = 1, no force, thermal with correction, FP32 storage, all
+ * sides periodic. */
 void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p);
 
 /* Exact device bytes tclbm_create needs in dev_buf for these parameters
@@ -116,19 +121,21 @@ size_t tclbm_state_bytes(const tclbm_params *p);
  * rho, ux, uy, T: host, nx*ny each (T ignored when thermal = 0).
  * ax_field, ay_field: host per-node acceleration (nullable; when given they
  * replace the uniform ax, ay).  hip_stream: a hipStream_t (NULL: default).
- * All sides start PERIODIC.  On error *out is NULL and nothing is kept. */
+ * Boundaries come from p->bc (E_INVALID if unpaired or WALL on an x side).
+ * On error *out is NULL and nothing is kept. */
 tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
                           const double *rho, const double *ux, const double *uy, const double *T,
                           const double *ax_field, const double *ay_field, tclbm_handle *out);
 
-/* Set the boundary kind of one side and, for WALL, its velocity and
- * temperature.  Takes effect from the next step.  E_INVALID for WALL on an x
- * side, a periodic side whose opposite is not periodic after the call (set
- * both sides of an axis before stepping: the pair is checked at step time). */
+/* Change the boundary kind of one side and, for WALL, its velocity and
+ * temperature, from the next step on (the state is left as it is).
+ * E_INVALID for WALL on an x side; an unpaired periodic axis is refused at
+ * step time (set both sides of an axis before stepping). */
 tclbm_status tclbm_set_bc(tclbm_handle h, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w);
 
 /* Enqueue nsteps time steps (asynchronous).  Long runs replay a captured HIP
- * graph of a fixed chunk of steps.  E_INVALID for an unpaired periodic axis. */
+ * graph of a fixed chunk of steps (not on the NULL stream, which cannot be
+ * captured).  E_INVALID for an unpaired periodic axis. */
 tclbm_status tclbm_step(tclbm_handle h, int64_t nsteps);
 
 /* As tclbm_step, then synchronise and report the elapsed device time of the
@@ -146,7 +153,7 @@ int64_t tclbm_steps_done(tclbm_handle h);
 
 /* Copy the raw post-collision population planes of the current state to the
  * host, in storage order [2][9][ny][nx] (f then h; h planes omitted when
- * thermal = 0), converted to float64 (16-bit forms: reference added back).
+ * thermal = 0), converted to float64 with the row reference added back.
  * out must hold 18*nx*ny doubles (9*nx*ny when athermal).  Synchronises. */
 tclbm_status tclbm_read_state(tclbm_handle h, double *out);
 
@@ -163,6 +170,24 @@ tclbm_status tclbm_destroy(tclbm_handle h);
  * measure the achievable HBM bandwidth next to the step kernel and to scale
  * hardware byte counters. */
 tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ---- batches: many resident lattices advanced by one launch per step ----
+ * A batch references existing handles (all with the same storage form and the
+ * same stream) and owns a small device table of their launch descriptors,
+ * ordered largest lattice first.  tclbm_batch_step advances every member by
+ * nsteps with one kernel launch per step (HIP-graph chunks when the stream is
+ * not NULL); results equal those of stepping each member alone, bitwise.
+ * While a member belongs to a batch, step it only through the batch; other
+ * calls on it (moments, read_state) are fine.  Changing a member's boundaries
+ * or tuning requires a new batch.  Destroy the batch before its members. */
+typedef struct tclbm_batch *tclbm_batch_handle;
+tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_handle *out);
+tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps);
+tclbm_status tclbm_batch_step_timed(tclbm_batch_handle b, int64_t nsteps, double *ms);
+int32_t tclbm_batch_size(tclbm_batch_handle b);
+int64_t tclbm_batch_waves(tclbm_batch_handle b);  /* wave64 work items per step */
+tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk);
+tclbm_status tclbm_batch_destroy(tclbm_batch_handle b);
 
 /* Static string for a status code; last HIP/validation message of a handle. */
 const char *tclbm_status_str(tclbm_status s);

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -69,6 +70,14 @@ bool valid_params(const tclbm_params *p) {
   if (p->heq_moments < 0 || p->heq_moments > 1) return false;
   if (p->h_collision < 0 || p->h_collision > 1) return false;
   if (p->accel_field != 0 && p->accel_field != 1) return false;
+  for (int q = 0; q < 4; ++q) {
+    if (p->bc[q] < kPeriodic || p->bc[q] > kWall) return false;
+    if (!(std::isfinite(p->wall_ux[q]) && std::isfinite(p->wall_uy[q]) && std::isfinite(p->wall_T[q]))) return false;
+    if (p->bc[q] == kWall && !(p->wall_T[q] > 0)) return false;
+  }
+  if (p->bc[kXlo] == kWall || p->bc[kXhi] == kWall) return false;
+  if ((p->bc[kXlo] == kPeriodic) != (p->bc[kXhi] == kPeriodic)) return false;
+  if ((p->bc[kYlo] == kPeriodic) != (p->bc[kYhi] == kPeriodic)) return false;
   return true;
 }
 
@@ -84,8 +93,8 @@ Plan plan_of(const tclbm_params *p) {
   const size_t esz = store_bytes(p->storage);
   const size_t plane = (size_t)pitch_of(p) * p->ny;
   pl.buf = up(plane * planes_of(p) * esz, kAlign);
-  pl.ref = up(sizeof(float) * 2 * 9 * (size_t)p->ny, kAlign);
   const size_t rsz = (p->storage == kF64) ? 8 : 4;
+  pl.ref = up(rsz * (2 + 2 * 9) * (size_t)p->ny, kAlign);
   pl.acc = p->accel_field ? up(2 * plane * rsz, kAlign) : 0;
   const long long n = (long long)p->nx * p->ny;
   pl.part = up(sizeof(double) * kNumSums * (size_t)((n + 255) / 256), kAlign);
@@ -120,8 +129,10 @@ void fill_kparams(tclbm_ctx *c) {
   k.ax = p.ax;
   k.ay = p.ay;
   for (int s = 0; s < 4; ++s) {
-    k.bc[s] = kPeriodic;
-    k.wall_T[s] = p.T0;
+    k.bc[s] = p.bc[s];
+    k.wall_ux[s] = p.wall_ux[s];
+    k.wall_uy[s] = p.wall_uy[s];
+    k.wall_T[s] = (p.bc[s] == kWall) ? p.wall_T[s] : p.T0;
   }
 }
 
@@ -133,10 +144,12 @@ void decompose(tclbm_ctx *c) {
   k.n_xtiles = (k.nx + k.tile_w - 1) / k.tile_w;
   int rows = c->strip_rows_req;
   if (rows <= 0) {
-    // enough waves to fill 256 CUs several times over, strips of >= 4 rows
+    // enough waves to fill 256 CUs several times over; long strips when the
+    // lattice is large (halo rows are re-pulled once per strip), short ones
+    // (down to a single row) when it is small
     const long long target = 16384;
-    long long r = ((long long)k.ny * k.n_xtiles + target - 1) / target;
-    rows = (int)(r < 4 ? 4 : r);
+    long long r = ((long long)k.ny * k.n_xtiles) / target;
+    rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }
   if (rows > k.ny) rows = k.ny;
   k.strip_rows = rows;
@@ -158,17 +171,41 @@ bool bc_pairs_ok(const KParams &k) {
     }                                                                         \
   } while (0)
 
-// Host copy of the product-form density equilibrium and of the energy
-// equilibrium at rest, for the 16-bit reference rows.
-void rest_refs(const tclbm_params &p, double rho, double T, float *rf, float *rh) {
-  double f[9], h[9];
-  const double RT = p.R * T;
-  feq9<double>(rho, 0.0, 0.0, RT, f);
-  heq9<double>(rho, 0.0, 0.0, RT, 2.0 / (p.gamma - 1.0), p.heq_moments, h);
-  for (int a = 0; a < 9; ++a) {
-    rf[a] = (float)f[a];
-    rh[a] = p.thermal ? (float)h[a] : 0.0f;
+// Per-row rest-state reference: (rho_r, theta_r) from the row means of the
+// initial fields, and the pull shifts r_a(y - e_ay) - r_a(y), s_a(...) - s_a(y),
+// evaluated in double from the values the kernels will see (rounded to the
+// compute type) so that writer and reader agree exactly.
+template <class R>
+void build_refs(const tclbm_params &p, const double *rho, const double *T, std::vector<R> &out) {
+  const int ny = p.ny, nx = p.nx;
+  const bool yper = p.bc[kYlo] == kPeriodic;
+  const double b = 2.0 / (p.gamma - 1.0);
+  out.assign((size_t)(2 + 18) * ny, R(0));
+  R *rr = out.data();
+  R *shF = rr + 2 * ny;
+  R *shH = shF + 9 * ny;
+  std::vector<double> rpop(9 * (size_t)ny), spop(9 * (size_t)ny);
+  for (int y = 0; y < ny; ++y) {
+    double rs = 0, ts = 0;
+    for (int x = 0; x < nx; ++x) {
+      rs += rho[(size_t)y * nx + x];
+      ts += p.thermal ? T[(size_t)y * nx + x] : p.T0;
+    }
+    rr[2 * y] = (R)(rs / nx);
+    rr[2 * y + 1] = (R)(p.R * (p.thermal ? ts / nx : p.T0));
+    RowRef<double> q = make_ref<double>((double)rr[2 * y], (double)rr[2 * y + 1], b, p.heq_moments);
+    ref_pops<double>(q, p.thermal, p.heq_moments, &rpop[9 * (size_t)y], &spop[9 * (size_t)y]);
   }
+  static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  for (int y = 0; y < ny; ++y)
+    for (int a = 0; a < 9; ++a) {
+      int sy = y - ey[a];
+      if (ey[a] == 0) continue;
+      if (yper) sy = (sy + ny) % ny;
+      else if (sy < 0 || sy >= ny) continue;
+      shF[9 * y + a] = (R)(rpop[9 * (size_t)sy + a] - rpop[9 * (size_t)y + a]);
+      shH[9 * y + a] = (R)(spop[9 * (size_t)sy + a] - spop[9 * (size_t)y + a]);
+    }
 }
 
 tclbm_status launch_steps(tclbm_ctx *c, int64_t n) {
@@ -223,7 +260,8 @@ tclbm_status do_steps(tclbm_ctx *c, int64_t n) {
     set_err(c, "periodic sides must come in pairs");
     return TCLBM_E_INVALID;
   }
-  const int ch = c->graph_chunk;
+  // the legacy NULL stream cannot be captured: plain launches there
+  const int ch = c->stream ? c->graph_chunk : 0;
   if (ch >= 2 && n >= 2 * (int64_t)ch) {
     if (c->cur != 0) {
       tclbm_status st = launch_steps(c, 1);
@@ -261,6 +299,10 @@ void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p) {
   p->thermal = 1;
   p->correction = 1;
   p->storage = TCLBM_STORE_F32;
+  for (int q = 0; q < 4; ++q) {
+    p->bc[q] = TCLBM_BC_PERIODIC;
+    p->wall_T[q] = 1.0;
+  }
 }
 
 size_t tclbm_state_bytes(const tclbm_params *p) {
@@ -294,31 +336,35 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
   c->esz = store_bytes(p->storage);
   c->buf[0] = c->base;
   c->buf[1] = c->base + pl.buf;
-  float *refs = reinterpret_cast<float *>(c->base + 2 * pl.buf);
+  char *refs = c->base + 2 * pl.buf;
+  const size_t rsz = (p->storage == kF64) ? 8 : 4;
   char *acc = c->base + 2 * pl.buf + pl.ref;
   c->partials = reinterpret_cast<double *>(acc + pl.acc);
   c->nparts = (int)((n + 255) / 256);
   c->cur = 0;
   c->graph_chunk = 32;
   fill_kparams(c);
-  c->k.refF = refs;
-  c->k.refH = refs + 9 * p->ny;
+  c->k.rowref = refs;
+  c->k.shiftF = refs + rsz * 2 * p->ny;
+  c->k.shiftH = refs + rsz * (2 + 9) * p->ny;
   decompose(c);
 
   tclbm_status st = TCLBM_OK;
   double *tmp = nullptr;
   do {
-    // per-row rest-state references (used by the 16-bit storage forms)
-    std::vector<float> ref(2 * 9 * (size_t)p->ny);
-    for (int y = 0; y < p->ny; ++y) {
-      double rs = 0, ts = 0;
-      for (int x = 0; x < p->nx; ++x) {
-        rs += rho[(size_t)y * p->nx + x];
-        ts += p->thermal ? T[(size_t)y * p->nx + x] : p->T0;
-      }
-      rest_refs(*p, rs / p->nx, ts / p->nx, &ref[(size_t)y * 9], &ref[(size_t)(p->ny + y) * 9]);
+    // per-row rest-state references of the deviation storage
+    hipError_t e;
+    if (p->storage == kF64) {
+      std::vector<double> ref;
+      build_refs<double>(*p, rho, T, ref);
+      e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    } else {
+      std::vector<float> ref;
+      build_refs<float>(*p, rho, T, ref);
+      e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
-    hipError_t e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) { set_err(c, "ref upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
     if (p->accel_field) {
       const size_t plane = (size_t)c->k.plane;
@@ -534,6 +580,179 @@ tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_
     return TCLBM_E_INVALID;
   hipError_t e = launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? TCLBM_OK : TCLBM_E_DEVICE;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches ---
+struct tclbm_batch {
+  std::vector<tclbm_handle> m;  // members, in table order
+  int storage;
+  hipStream_t stream;
+  KParams *d_tab;    // device table (src/dst of the even steps)
+  int *d_start;      // device prefix sums of waves per member
+  int total_waves;
+  int graph_chunk;
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int parity;        // 0: members' current state in the table's src
+  char err[256];
+};
+
+static void batch_drop_graph(tclbm_batch *b) {
+  if (b->graph_ok) hipGraphExecDestroy(b->graph);
+  b->graph_ok = false;
+}
+
+static tclbm_status batch_launch(tclbm_batch *b, int64_t n) {
+  for (int64_t s = 0; s < n; ++s) {
+    hipError_t e = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, b->parity,
+                                     b->stream);
+    if (e != hipSuccess) {
+      snprintf(b->err, sizeof(b->err), "batch launch: %s", hipGetErrorString(e));
+      return TCLBM_E_DEVICE;
+    }
+    b->parity ^= 1;
+  }
+  return TCLBM_OK;
+}
+
+extern "C" {
+
+tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_handle *out) {
+  if (!out) return TCLBM_E_INVALID;
+  *out = nullptr;
+  if (!members || n <= 0) return TCLBM_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    tclbm_handle h = members[i];
+    if (!h || h->unstable) return TCLBM_E_INVALID;
+    if (h->p.storage != members[0]->p.storage || h->stream != members[0]->stream) return TCLBM_E_INVALID;
+    if (!bc_pairs_ok(h->k)) return TCLBM_E_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (members[j] == h) return TCLBM_E_INVALID;
+  }
+  tclbm_batch *b = new (std::nothrow) tclbm_batch();
+  if (!b) return TCLBM_E_NOMEM;
+  b->m.assign(members, members + n);
+  // largest members first: their waves start first and the tail is short ones
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto work = [&](int i) { return (long long)b->m[i]->k.n_xtiles * b->m[i]->k.n_strips * b->m[i]->k.strip_rows; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  std::vector<tclbm_handle> sorted(n);
+  for (int i = 0; i < n; ++i) sorted[i] = b->m[order[i]];
+  b->m = sorted;
+  b->storage = members[0]->p.storage;
+  b->stream = members[0]->stream;
+  b->graph_chunk = 16;
+  std::vector<KParams> tab(n);
+  std::vector<int> start(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    tclbm_handle h = b->m[i];
+    tab[i] = h->k;
+    tab[i].src = h->buf[h->cur];
+    tab[i].dst = h->buf[1 - h->cur];
+    start[i + 1] = start[i] + h->k.n_xtiles * h->k.n_strips;
+  }
+  b->total_waves = start[n];
+  hipError_t e = hipMalloc(&b->d_tab, sizeof(KParams) * n);
+  if (e == hipSuccess) e = hipMalloc(&b->d_start, sizeof(int) * (n + 1));
+  if (e == hipSuccess) e = hipMemcpy(b->d_tab, tab.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_start, start.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (b->d_tab) hipFree(b->d_tab);
+    if (b->d_start) hipFree(b->d_start);
+    delete b;
+    return TCLBM_E_DEVICE;
+  }
+  *out = b;
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
+  if (!b || nsteps < 0) return TCLBM_E_INVALID;
+  for (tclbm_handle h : b->m)
+    if (h->unstable) return TCLBM_E_STATE;
+  const int ch = b->stream ? b->graph_chunk : 0;
+  int64_t n = nsteps;
+  tclbm_status st = TCLBM_OK;
+  if (ch >= 2 && n >= 2 * (int64_t)ch) {
+    if (b->parity) {
+      st = batch_launch(b, 1);
+      --n;
+    }
+    if (st == TCLBM_OK && !b->graph_ok) {
+      hipGraph_t g;
+      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      hipError_t le = hipSuccess;
+      for (int s = 0; s < ch && le == hipSuccess && e == hipSuccess; ++s)
+        le = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, s & 1, b->stream);
+      hipError_t ee = (e == hipSuccess) ? hipStreamEndCapture(b->stream, &g) : e;
+      if (e != hipSuccess || le != hipSuccess || ee != hipSuccess) {
+        if (e == hipSuccess && ee == hipSuccess) hipGraphDestroy(g);
+        snprintf(b->err, sizeof(b->err), "batch capture failed");
+        return TCLBM_E_DEVICE;
+      }
+      ee = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ee != hipSuccess) return TCLBM_E_DEVICE;
+      b->graph_ok = true;
+    }
+    while (st == TCLBM_OK && n >= ch) {
+      if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return TCLBM_E_DEVICE;
+      n -= ch;  // an even chunk leaves the parity unchanged
+    }
+  }
+  if (st == TCLBM_OK) st = batch_launch(b, n);
+  // members' bookkeeping: the state now lives in the buffer the parity names
+  const int64_t done = nsteps - (st == TCLBM_OK ? 0 : n);
+  for (tclbm_handle h : b->m) {
+    h->steps += done;
+    if (done & 1) h->cur = 1 - h->cur;
+  }
+  return st;
+}
+
+tclbm_status tclbm_batch_step_timed(tclbm_batch_handle b, int64_t nsteps, double *ms) {
+  if (!b || !ms) return TCLBM_E_INVALID;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return TCLBM_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return TCLBM_E_DEVICE;
+  }
+  hipEventRecord(e0, b->stream);
+  tclbm_status st = tclbm_batch_step(b, nsteps);
+  hipEventRecord(e1, b->stream);
+  hipError_t e = hipEventSynchronize(e1);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+  *ms = f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TCLBM_OK) return st;
+  return e == hipSuccess ? TCLBM_OK : TCLBM_E_DEVICE;
+}
+
+int32_t tclbm_batch_size(tclbm_batch_handle b) { return b ? (int32_t)b->m.size() : -1; }
+
+int64_t tclbm_batch_waves(tclbm_batch_handle b) { return b ? b->total_waves : -1; }
+
+tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk) {
+  if (!b || chunk < 0 || chunk == 1 || (chunk & 1)) return TCLBM_E_INVALID;
+  b->graph_chunk = chunk;
+  batch_drop_graph(b);
+  return TCLBM_OK;
+}
+
+tclbm_status tclbm_batch_destroy(tclbm_batch_handle b) {
+  if (!b) return TCLBM_E_INVALID;
+  (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  (void)hipFree(b->d_tab);
+  (void)hipFree(b->d_start);
+  delete b;
+  return TCLBM_OK;
 }
 
 }  // extern "C"

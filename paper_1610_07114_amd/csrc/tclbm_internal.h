@@ -25,7 +25,10 @@ struct KParams {
   double wall_ux[4], wall_uy[4], wall_T[4];
   double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;
   const void *axf, *ayf;          // per-node acceleration, compute type, pitch layout (nullable)
-  const float *refF, *refH;       // per-row reference populations [ny][9] (16-bit storage)
+  // per-row rest-state reference (compute type): rowref[2y] = rho_r,
+  // rowref[2y+1] = theta_r = R T_r; shiftF/H[9y + a] = r_a(row y - e_ay) - r_a(y)
+  // (zero where that row is outside a non-periodic side)
+  const void *rowref, *shiftF, *shiftH;
   // march decomposition
   int tile_w, lane_off, n_xtiles, strip_rows, n_strips;
 };
@@ -37,6 +40,9 @@ size_t store_bytes(int storage);
 
 hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
 int step_waves_per_block();
+// one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
+hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
+                             int storage, int parity, hipStream_t s);
 hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
                        const double *d_uy, const double *d_T, hipStream_t s);
 // fields (device, double, nx*ny each, nullable) and per-block partial sums

@@ -2,9 +2,11 @@
 //
 // Data layout (per population buffer): 9 planes of f then 9 planes of h
 // (h omitted when athermal), each plane ny rows of `pitch` elements, x fastest.
-// A buffer holds post-collision populations at their own node; the next step
-// pulls them (f_a(x, t+1) = P_a(x - e_a, t)), so one step reads 18 and writes
-// 18 values per node: one HBM pass.
+// A buffer holds post-collision populations at their own node, stored as
+// deviations from the rest-state reference of their row; the next step pulls
+// them (f_a(x, t+1) = P_a(x - e_a, t)) and adds the per-row shift
+// r_a(source row) - r_a(own row).  One step reads 18 and writes 18 values per
+// node: one HBM pass.
 //
 // Step kernel decomposition: one wave64 owns a tile of tile_w consecutive
 // columns (plus one halo column on each side, two on the left when x is not
@@ -36,33 +38,29 @@ struct Store;
 template <>
 struct Store<kF32> {
   using T = float;
-  static __device__ __forceinline__ float ld(const T *p, long long i, float) { return p[i]; }
-  static __device__ __forceinline__ void st(T *p, long long i, float v, float) { p[i] = v; }
+  static __device__ __forceinline__ float ld(const T *p, long long i) { return p[i]; }
+  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = v; }
 };
 template <>
 struct Store<kF64> {
   using T = double;
-  static __device__ __forceinline__ double ld(const T *p, long long i, double) { return p[i]; }
-  static __device__ __forceinline__ void st(T *p, long long i, double v, double) { p[i] = v; }
+  static __device__ __forceinline__ double ld(const T *p, long long i) { return p[i]; }
+  static __device__ __forceinline__ void st(T *p, long long i, double v) { p[i] = v; }
 };
 template <>
-struct Store<kF16> {  // deviation from the row reference, IEEE half, RNE
+struct Store<kF16> {  // IEEE half, round to nearest even
   using T = unsigned short;
-  static __device__ __forceinline__ float ld(const T *p, long long i, float ref) {
-    return ref + __half2float(__ushort_as_half(p[i]));
-  }
-  static __device__ __forceinline__ void st(T *p, long long i, float v, float ref) {
-    p[i] = __half_as_ushort(__float2half_rn(v - ref));
-  }
+  static __device__ __forceinline__ float ld(const T *p, long long i) { return __half2float(__ushort_as_half(p[i])); }
+  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = __half_as_ushort(__float2half_rn(v)); }
 };
 template <>
-struct Store<kBF16> {  // deviation from the row reference, bfloat16, RNE
+struct Store<kBF16> {  // bfloat16, round to nearest even
   using T = unsigned short;
-  static __device__ __forceinline__ float ld(const T *p, long long i, float ref) {
-    return ref + __bfloat162float(__ushort_as_bfloat16(p[i]));
+  static __device__ __forceinline__ float ld(const T *p, long long i) {
+    return __bfloat162float(__ushort_as_bfloat16(p[i]));
   }
-  static __device__ __forceinline__ void st(T *p, long long i, float v, float ref) {
-    p[i] = __bfloat16_as_ushort(__float2bfloat16(v - ref));
+  static __device__ __forceinline__ void st(T *p, long long i, float v) {
+    p[i] = __bfloat16_as_ushort(__float2bfloat16(v));
   }
 };
 
@@ -74,9 +72,6 @@ template <>
 struct Real<kF64> {
   using T = double;
 };
-
-template <int S>
-constexpr bool kDev = (S == kF16 || S == kBF16);
 
 // ------------------------------------------------------------- utilities ---
 template <class R>
@@ -91,7 +86,8 @@ __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   c.w4 = (R)k.w4;
   c.wh = (R)k.wh;
   c.inv_tau_hf = (R)k.inv_tau_hf;
-  c.inv_bR2 = (R)(2.0 / (k.b * k.R));
+  c.two_b = (R)(2.0 / k.b);
+  c.inv_RT0 = (R)(1.0 / (k.R * k.T0));
   c.thermal = k.thermal;
   c.correction = k.correction;
   c.heq_mode = k.heq_mode;
@@ -149,14 +145,23 @@ __device__ __forceinline__ void node_accel(const KParams &k, int y, int x, R &ax
   }
 }
 
+template <class R>
+__device__ __forceinline__ RowRef<R> row_ref(const KParams &k, const Consts<R> &c, int y) {
+  const R *rr = reinterpret_cast<const R *>(k.rowref);
+  return make_ref<R>(rr[2 * y], rr[2 * y + 1], c.b, c.heq_mode);
+}
+
 // Pull the populations that arrive at (col.xc, y): f_a = P_a(x - e_a).  Links
 // from outside a non-periodic side bounce back halfway at rest:
 // f_a = P_opp(a)(x) (for WALL rows those values are never used).
 template <int S>
 __device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
                                      typename Real<S>::T *f, typename Real<S>::T *h) {
+  using R = typename Real<S>::T;
   using ST = typename Store<S>::T;
   const ST *src = reinterpret_cast<const ST *>(k.src);
+  const R *shF = reinterpret_cast<const R *>(k.shiftF) + 9 * y;
+  const R *shH = reinterpret_cast<const R *>(k.shiftH) + 9 * y;
   int ym, yp;
   bool outB, outT;
   if (k.bc[kYlo] == kPeriodic) {
@@ -169,65 +174,91 @@ __device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
     ym = outB ? y : y - 1;
     yp = outT ? y : y + 1;
   }
-  const long long own = (long long)y * k.pitch + col.xc;
+  // element offsets inside a plane (< 2^31): rows are wave-uniform, columns per lane
+  const unsigned rm = (unsigned)ym * k.pitch, rc = (unsigned)y * k.pitch, rp = (unsigned)yp * k.pitch;
+  const long long hoff = 9 * k.plane;
+  if (k.bc[kXlo] == kPeriodic && !outB && !outT) {
+    // fast path: every link comes from inside the lattice
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const unsigned off = (kEy[a] > 0 ? rm : (kEy[a] < 0 ? rp : rc)) +
+                           (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
+      const ST *base = src + a * k.plane;
+      f[a] = Store<S>::ld(base, off);
+      if (kEy[a] != 0) f[a] += shF[a];
+      if (k.thermal) {
+        h[a] = Store<S>::ld(base + hoff, off);
+        if (kEy[a] != 0) h[a] += shH[a];
+      }
+    }
+    return;
+  }
+  // edge tiles and rows: links from outside a non-periodic side bounce back
+  // halfway at rest, f_a = P_opp(a)(x) (rest state symmetric: no shift)
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
     const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
-    const int sy = kEy[a] > 0 ? ym : (kEy[a] < 0 ? yp : y);
+    const unsigned sr = kEy[a] > 0 ? rm : (kEy[a] < 0 ? rp : rc);
     const bool oy = kEy[a] > 0 ? outB : (kEy[a] < 0 ? outT : false);
     const bool bb = ox || oy;
-    const int pa = bb ? kOpp[a] : a;
-    const int ry = bb ? y : sy;
-    const long long idx = (long long)pa * k.plane + (bb ? own : (long long)sy * k.pitch + sx);
-    float rf = 0.f, rh = 0.f;
-    if (kDev<S>) {
-      rf = k.refF[ry * 9 + pa];
-      rh = k.refH[ry * 9 + pa];
+    const ST *base = src + (bb ? kOpp[a] : a) * k.plane;
+    const unsigned off = bb ? rc + (unsigned)col.xc : sr + (unsigned)sx;
+    f[a] = Store<S>::ld(base, off);
+    if (kEy[a] != 0 && !bb) f[a] += shF[a];
+    if (k.thermal) {
+      h[a] = Store<S>::ld(base + hoff, off);
+      if (kEy[a] != 0 && !bb) h[a] += shH[a];
     }
-    f[a] = Store<S>::ld(src, idx, rf);
-    if (k.thermal) h[a] = Store<S>::ld(src, idx + 9 * k.plane, rh);
   }
 }
 
 // Populations of a WALL row node by non-equilibrium extrapolation from the
-// adjacent fluid node (fI, hI, mI):
-// X(x_b) = X^eq(rho_w, u_w, T_w) + [X(x_f) - X^eq(rho_f, u_f, T_f)].
-// fw holds on entry the populations pulled at the wall node; those that came
-// from the fluid and the tangential ones fix rho_w (default reading).
+// adjacent fluid node (I):
+// X(x_b) = X^eq(rho_w, u_w, T_w) + [X(x_f) - X^eq(rho_f, u_f, T_f)],
+// in deviations: d_w = (f^eq_w - r_w) - (f^eq_I - r_I) + d_I.
+// On entry dw holds the deviations pulled at the wall node; those that came
+// from the fluid and the tangential ones fix rho_w (default reading): with the
+// rest reference, k0 + 2 k_in = rho_r + the same combination of deviations.
 template <class R>
-__device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const R *fI, const R *hI,
-                                          const Macro<R> &mI, R aI_n, R aW_n, R *fw, R *hw) {
+__device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const RowRef<R> &qw,
+                                          const RowRef<R> &qI, const R *dI, const R *gI, const Macro<R> &mI,
+                                          R aI_n, R aW_n, R *dw, R *gw) {
   const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
-  const R Tw = k.thermal ? (R)k.wall_T[side] : c.T0;
-  R rw;
+  const R thw = k.thermal ? c.R_ * (R)k.wall_T[side] : c.R_ * c.T0;
+  R drw;
   if (k.wall_rho == 1) {
-    rw = mI.rho;
+    drw = mI.drho + (qI.rho - qw.rho);
   } else if (k.wall_rho == 2) {
-    rw = (mI.rho * c.R_ * mI.T + mI.rho * aI_n) / (c.R_ * Tw);
+    drw = (mI.rho * mI.th + mI.rho * aI_n) / thw - qw.rho;
   } else {
     // bottom: links from the fluid are e_y = -1 (4, 7, 8); top: e_y = +1 (2, 5, 6)
-    R k0 = fw[0] + fw[1] + fw[3];
-    R kin = (side == kYlo) ? (fw[4] + fw[7] + fw[8]) : (fw[2] + fw[5] + fw[6]);
-    R un = (side == kYlo) ? -uwy : uwy;
-    rw = (k0 + R(2) * kin) / (R(1) + un - R(0.5) * aW_n);
+    const R D = (dw[0] + dw[1] + dw[3]) +
+                R(2) * ((side == kYlo) ? (dw[4] + dw[7] + dw[8]) : (dw[2] + dw[5] + dw[6]));
+    const R un = (side == kYlo) ? -uwy : uwy;
+    const R den = R(1) + un - R(0.5) * aW_n;
+    drw = (D - qw.rho * (un - R(0.5) * aW_n)) / den;
   }
+  const R dthw = thw - qw.th;
   R ew[9], ef[9];
-  feq9(rw, uwx, uwy, c.R_ * Tw, ew);
-  feq9(mI.rho, mI.ux, mI.uy, c.R_ * mI.T, ef);
+  feq_dev(qw, drw, uwx, uwy, dthw, ew);
+  feq_dev(qI, mI.drho, mI.ux, mI.uy, mI.dth, ef);
 #pragma unroll
-  for (int a = 0; a < 9; ++a) fw[a] = ew[a] + (fI[a] - ef[a]);
+  for (int a = 0; a < 9; ++a) dw[a] = ew[a] - ef[a] + dI[a];
   if (k.thermal) {
-    heq9(rw, uwx, uwy, c.R_ * Tw, c.b, c.heq_mode, ew);
-    heq9(mI.rho, mI.ux, mI.uy, c.R_ * mI.T, c.b, c.heq_mode, ef);
+    const R Ew = R(0.5) * (c.b * thw + uwx * uwx + uwy * uwy);
+    const R sgw = drw * Ew + qw.rho * (R(0.5) * c.b * dthw + R(0.5) * (uwx * uwx + uwy * uwy));
+    heq_dev(c, qw, drw, uwx, uwy, dthw, sgw, ew);
+    heq_dev(c, qI, mI.drho, mI.ux, mI.uy, mI.dth, mI.sg, ef);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) hw[a] = ew[a] + (hI[a] - ef[a]);
+    for (int a = 0; a < 9; ++a) gw[a] = ew[a] - ef[a] + gI[a];
   }
 }
 
 template <class R>
 struct RowState {
-  R f[9], h[9];
+  R f[9], h[9];  // deviations from the row reference
+  RowRef<R> q;
   Macro<R> m;
   R qx, qy;  // u (1 - theta)
 };
@@ -236,8 +267,8 @@ template <class R>
 __device__ __forceinline__ void finish(const KParams &k, const Consts<R> &c, int y, int xc, RowState<R> &s) {
   R ax, ay;
   node_accel<R>(k, y, xc, ax, ay);
-  s.m = macros(c, s.f, s.h, ax, ay);
-  R om = R(1) - s.m.T / c.T0;
+  s.m = macros(c, s.q, s.f, s.h, ax, ay);
+  R om = R(1) - s.m.th * c.inv_RT0;
   s.qx = s.m.ux * om;
   s.qy = s.m.uy * om;
 }
@@ -250,6 +281,7 @@ __device__ __forceinline__ bool is_wall_row(const KParams &k, int y) {
 template <int S>
 __device__ __forceinline__ void get_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                         const Col &col, RowState<typename Real<S>::T> &s) {
+  s.q = row_ref(k, c, y);
   pull<S>(k, y, col, s.f, s.h);
   finish(k, c, y, col.xc, s);
 }
@@ -262,13 +294,14 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   using R = typename Real<S>::T;
   const int side = (y == 0) ? kYlo : kYhi;
   const int yf = (y == 0) ? 1 : y - 1;
+  s.q = row_ref(k, c, y);
   if (k.wall_rho == 0) pull<S>(k, y, col, s.f, s.h);
   R axI, ayI, axW, ayW;
   node_accel<R>(k, yf, col.xc, axI, ayI);
   node_accel<R>(k, y, col.xc, axW, ayW);
   const R aI_n = (side == kYlo) ? -ayI : ayI;
   const R aW_n = (side == kYlo) ? -ayW : ayW;
-  wall_node<R>(k, c, side, in.f, in.h, in.m, aI_n, aW_n, s.f, s.h);
+  wall_node<R>(k, c, side, s.q, in.q, in.f, in.h, in.m, aI_n, aW_n, s.f, s.h);
   finish(k, c, y, col.xc, s);
 }
 
@@ -305,19 +338,14 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   R ax, ay;
   node_accel<R>(k, y, col.xc, ax, ay);
   R P[9], Q[9];
-  collide(c, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
+  collide(c, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
   if (!store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
-  const long long own = (long long)y * k.pitch + col.xc;
+  const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    float rf = 0.f, rh = 0.f;
-    if (kDev<S>) {
-      rf = k.refF[y * 9 + a];
-      rh = k.refH[y * 9 + a];
-    }
-    Store<S>::st(dst, (long long)a * k.plane + own, P[a], rf);
-    if (k.thermal) Store<S>::st(dst, (long long)(a + 9) * k.plane + own, Q[a], rh);
+    Store<S>::st(dst + a * k.plane, own, P[a]);
+    if (k.thermal) Store<S>::st(dst + (a + 9) * k.plane, own, Q[a]);
   }
 }
 
@@ -326,12 +354,10 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 // ------------------------------------------------------------ step kernel ---
 constexpr int kStepWaves = 4;
 
+// The march of one wave over its (x tile, strip) of lattice k.
 template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
+__device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
   using R = typename Real<S>::T;
-  const int lane = threadIdx.x & 63;
-  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
-  if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
   const int strip = wave / k.n_xtiles;
   const int xt = wave - strip * k.n_xtiles;
   const int r0 = strip * k.strip_rows;
@@ -398,6 +424,54 @@ __global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
   }
 }
 
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
+  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
+  march<S>(k, wave, threadIdx.x & 63);
+}
+
+// Batched step: one launch advances every lattice of a table by one step.
+// wave_start[i] is the first global wave of instance i (prefix sum of
+// n_xtiles * n_strips, wave_start[n] = total); waves of one instance are
+// contiguous, ordered as the table (the autotuner orders the table).
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel(const KParams *__restrict__ tab,
+                                                                     const int *__restrict__ wave_start,
+                                                                     int n_inst, int parity) {
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
+  if (wave >= wave_start[n_inst]) return;
+  int lo = 0, hi = n_inst - 1;  // last instance whose start <= wave
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wave_start[mid] <= wave) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  KParams k = tab[lo];
+  if (parity) {  // odd steps run from the second buffer
+    const void *t = k.src;
+    k.src = k.dst;
+    k.dst = const_cast<void *>(t);
+  }
+  march<S>(k, wave - wave_start[lo], threadIdx.x & 63);
+}
+
+hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
+                             int storage, int parity, hipStream_t s) {
+  if (total_waves <= 0) return hipSuccess;
+  const int blocks = (total_waves + kStepWaves - 1) / kStepWaves;
+  dim3 grid(blocks), block(64 * kStepWaves);
+  switch (storage) {
+    case kF32: hipLaunchKernelGGL(batch_step_kernel<kF32>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    case kF16: hipLaunchKernelGGL(batch_step_kernel<kF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    case kBF16: hipLaunchKernelGGL(batch_step_kernel<kBF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    case kF64: hipLaunchKernelGGL(batch_step_kernel<kF64>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 int step_waves_per_block() { return kStepWaves; }
 
 hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
@@ -426,8 +500,10 @@ size_t store_bytes(int storage) {
 
 // ------------------------------------------------------------ init kernel ---
 // P_a(x) = fbar^init_a(x + e_a) so that the first pull returns the initial
-// state; a link leaving through a bounce-back side stores the opposite
-// population of the same node (the value that bounces back into it).
+// state fbar = f^eq - S/2, hbar = h^eq (Sections 3-4); the stored deviation is
+// taken against the storing row (the reader adds r_a(source) - r_a(own) back).
+// A link leaving through a non-periodic side stores the opposite population of
+// the same node (the value that bounces back into it).
 template <int S>
 __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho, const double *ux,
                                                    const double *uy, const double *T) {
@@ -450,28 +526,33 @@ __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho,
     if (yper) ty = (ty + k.ny) % k.ny;
     else if (ty < 0 || ty >= k.ny) out = true;
     int comp = a;
-    if (out) {  // bounce-back (or wall row: value unused)
+    if (out) {
       tx = x;
       ty = y;
       comp = kOpp[a];
     }
     const long long j = (long long)ty * k.nx + tx;
+    const RowRef<R> q = row_ref(k, c, ty);
     const R r = (R)rho[j], vx = (R)ux[j], vy = (R)uy[j];
-    const R t = k.thermal ? (R)T[j] : c.T0;
+    const R th = c.R_ * (k.thermal ? (R)T[j] : c.T0);
+    const R drho = r - q.rho, dth = th - q.th;
     R ax, ay;
     node_accel<R>(k, ty, tx, ax, ay);
     R fe[9], se[9], he[9];
-    feq9(r, vx, vy, c.R_ * t, fe);
+    feq_dev(q, drho, vx, vy, dth, fe);
     source9(r, vx, vy, ax, ay, se);
-    float rf = 0.f, rh = 0.f;
-    if (kDev<S>) {
-      rf = k.refF[y * 9 + a];
-      rh = k.refH[y * 9 + a];
+    // shift of the reader at (tx, ty) for direction a: r_a(y) - r_a(ty)
+    R shf = R(0), shh = R(0);
+    if (!out && kEy[a] != 0) {
+      shf = reinterpret_cast<const R *>(k.shiftF)[9 * ty + a];
+      shh = reinterpret_cast<const R *>(k.shiftH)[9 * ty + a];
     }
-    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp], rf);
+    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp] - shf);
     if (k.thermal) {
-      heq9(r, vx, vy, c.R_ * t, c.b, c.heq_mode, he);
-      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp], rh);
+      const R E = R(0.5) * (c.b * th + vx * vx + vy * vy);
+      const R sg = drho * E + q.rho * (R(0.5) * c.b * dth + R(0.5) * (vx * vx + vy * vy));
+      heq_dev(c, q, drho, vx, vy, dth, sg, he);
+      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp] - shh);
     }
   }
 }
@@ -520,21 +601,21 @@ __global__ __launch_bounds__(kMomThreads) void moments_kernel(KParams k, double 
     } else {
       get_row<S>(k, c, y, col, s);
     }
-    const double r = (double)s.m.rho, u = (double)s.m.ux, w = (double)s.m.uy, t = (double)s.m.T;
+    const double r = (double)s.q.rho + (double)s.m.drho, u = (double)s.m.ux, w = (double)s.m.uy;
+    const double tmt0 = ((double)s.q.th - k.R * k.T0 + (double)s.m.dth) / k.R;  // T - T0
+    const double t = k.T0 + tmt0;
     if (frho) frho[i] = r;
     if (fux) fux[i] = u;
     if (fuy) fuy[i] = w;
     if (fT) fT[i] = t;
-    double hs = 0.0;
-    if (k.thermal)
-      for (int a = 0; a < 9; ++a) hs += (double)s.h[a];
+    const double hs = k.thermal ? (double)s.q.rho * (double)s.q.E + (double)s.m.sg : 0.0;
     const bool bad = !(isfinite(r) && isfinite(u) && isfinite(w) && isfinite(t));
     v[kSumMass] = r;
     v[kSumMx] = r * u;
     v[kSumMy] = r * w;
     v[kSumE] = hs;
     v[kSumKin] = 0.5 * r * (u * u + w * w);
-    v[kSumNu] = w * (t - k.T0);
+    v[kSumNu] = w * tmt0;
     v[kSumRhoMin] = bad ? -1.0 : r;
     v[kSumTMin] = bad ? -1.0 : t;
     v[kSumBad] = bad ? 1.0 : 0.0;
@@ -590,6 +671,7 @@ hipError_t launch_moments(const KParams &k, int storage, double *d_rho, double *
 // ----------------------------------------------------- raw state readback ---
 template <int S>
 __global__ __launch_bounds__(256) void read_state_kernel(KParams k, double *out) {
+  using R = typename Real<S>::T;
   using ST = typename Store<S>::T;
   const long long n = (long long)k.nx * k.ny;
   const int np = k.thermal ? 18 : 9;
@@ -599,9 +681,12 @@ __global__ __launch_bounds__(256) void read_state_kernel(KParams k, double *out)
   const long long node = i - (long long)a * n;
   const int y = (int)(node / k.nx), x = (int)(node - (long long)y * k.nx);
   const ST *src = reinterpret_cast<const ST *>(k.src);
-  float ref = 0.f;
-  if (kDev<S>) ref = (a < 9) ? k.refF[y * 9 + a] : k.refH[y * 9 + (a - 9)];
-  out[i] = (double)Store<S>::ld(src, (long long)a * k.plane + (long long)y * k.pitch + x, ref);
+  const R *rr = reinterpret_cast<const R *>(k.rowref);
+  const RowRef<double> q = make_ref<double>((double)rr[2 * y], (double)rr[2 * y + 1], k.b, k.heq_mode);
+  double r[9], s[9];
+  ref_pops<double>(q, k.thermal, k.heq_mode, r, s);
+  const double ref = (a < 9) ? r[a] : s[a - 9];
+  out[i] = ref + (double)Store<S>::ld(src, (long long)a * k.plane + (long long)y * k.pitch + x);
 }
 
 hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipStream_t s) {

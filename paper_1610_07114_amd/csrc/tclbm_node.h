@@ -8,6 +8,13 @@
 // (Section 4) are all applied in central-moment space, so one inverse transform
 // yields fbar* + S + C directly.  Moments are rho-weighted throughout
 // (kappa_pq = sum_a f_a (e_ax - u_x)^p (e_ay - u_y)^q).
+//
+// Deviation arithmetic: the state is held as d_a = fbar_a - r_a and
+// g_a = hbar_a - s_a, where r and s are the rest-state equilibria of the row
+// (density rho_r, theta_r = R T_r).  The central moments of r about u are known
+// in closed form (r is a product of 1-D factors with moments 1, -u, theta_r +
+// u^2), so every quantity below is formed as a difference of small numbers and
+// FP32 rounding acts on deviations, not on O(1) populations.  theta = R T.
 #pragma once
 
 #if defined(__HIPCC__) || defined(__HIP__)
@@ -37,8 +44,8 @@ TC_HD void fwd3(R m, R z, R p, R u, R &k0, R &k1, R &k2) {
 // populations at e = -1, 0, +1.
 template <class R>
 TC_HD void inv3(R c0, R c1, R c2, R u, R &m, R &z, R &p) {
-  R r1 = c1 + u * c0;           // first raw moment
-  R r2 = c2 + u * (c1 + r1);    // second raw moment
+  R r1 = c1 + u * c0;         // first raw moment
+  R r2 = c2 + u * (c1 + r1);  // second raw moment
   z = c0 - r2;
   p = R(0.5) * (r2 + r1);
   m = R(0.5) * (r2 - r1);
@@ -66,152 +73,231 @@ TC_HD void pops9(const R c[3][3], R ux, R uy, R *f) {
   inv3(bp[0], bp[1], bp[2], ux, f[6], f[2], f[5]);
 }
 
-// Cascaded equilibrium of the density DF in product form:
-// f_a = rho psi(e_ax, ux) psi(e_ay, uy), psi(0,u) = 1 - RT - u^2,
-// psi(+-1,u) = (RT + u^2 +- u)/2 (Eq. (7) with the local T, through Eq. (9)).
+// Rest-state reference of one row: r = rho_r psi(e_x) psi(e_y) with
+// psi(0) = 1 - theta_r, psi(+-1) = theta_r/2 (the density equilibrium at rest),
+// s = the energy equilibrium at rest; E = b theta_r/2, S2 = theta_r(E + theta_r)
+// and S22 its second and fourth raw moments per unit mass.
 template <class R>
-TC_HD void feq9(R rho, R ux, R uy, R RT, R *f) {
-  R x0 = R(1) - RT - ux * ux, xs = R(0.5) * (RT + ux * ux);
-  R xp = xs + R(0.5) * ux, xm = xs - R(0.5) * ux;
-  R y0 = R(1) - RT - uy * uy, ys = R(0.5) * (RT + uy * uy);
-  R yp = rho * (ys + R(0.5) * uy), ym = rho * (ys - R(0.5) * uy);
-  y0 *= rho;
-  f[0] = x0 * y0;
-  f[1] = xp * y0;
-  f[2] = x0 * yp;
-  f[3] = xm * y0;
-  f[4] = x0 * ym;
-  f[5] = xp * yp;
-  f[6] = xm * yp;
-  f[7] = xm * ym;
-  f[8] = xp * ym;
+struct RowRef {
+  R rho, th, E, S2, S22;
+};
+
+template <class R>
+TC_HD RowRef<R> make_ref(R rho, R th, R b, int heq_mode) {
+  RowRef<R> q;
+  q.rho = rho;
+  q.th = th;
+  q.E = R(0.5) * b * th;
+  q.S2 = th * (q.E + th);
+  q.S22 = (heq_mode == 1) ? R(0) : th * th * (q.E + R(2) * th);
+  return q;
 }
 
-// Equilibrium of the total-energy DF, E = (b RT + u^2)/2.
-// mode 0: central moments about u of the continuous total-energy density
-//   (rho E, rho RT u, rho RT(E+RT) on both axes, rho u_y RT^2, rho u_x RT^2,
-//    rho RT^2 (E + 2RT)); mode 1: the explicit form of Section 4 (higher raw
-//   moments zero).
+// Rest populations of the reference (host tables and tests).
 template <class R>
-TC_HD void heq9(R rho, R ux, R uy, R RT, R b, int mode, R *h) {
-  R u2 = ux * ux + uy * uy;
-  R E = R(0.5) * (b * RT + u2);
-  if (mode == 1) {
-    R A = E + RT, B = E + R(2) * RT, C = RT * A;
-    R hx = R(0.5) * rho, hq = R(0.25) * rho * B * ux * uy;
-    h[0] = rho * (E - B * u2 - R(2) * C);
-    R sx = B * ux * ux + C, sy = B * uy * uy + C;
-    h[1] = hx * (A * ux + sx);
-    h[3] = hx * (-A * ux + sx);
-    h[2] = hx * (A * uy + sy);
-    h[4] = hx * (-A * uy + sy);
-    h[5] = hq;
-    h[6] = -hq;
-    h[7] = hq;
-    h[8] = -hq;
+TC_HD void ref_pops(const RowRef<R> &q, int thermal, int heq_mode, R *r, R *s) {
+  const R p0 = R(1) - q.th, p1 = R(0.5) * q.th;
+  r[0] = q.rho * p0 * p0;
+  r[1] = r[2] = r[3] = r[4] = q.rho * p0 * p1;
+  r[5] = r[6] = r[7] = r[8] = q.rho * p1 * p1;
+  if (!thermal) {
+    for (int a = 0; a < 9; ++a) s[a] = R(0);
     return;
   }
-  R rRT = rho * RT;
-  R c[3][3];
-  c[0][0] = rho * E;
-  c[1][0] = rRT * ux;
-  c[0][1] = rRT * uy;
-  c[2][0] = rRT * (E + RT);
-  c[0][2] = c[2][0];
-  c[1][1] = R(0);
-  c[2][1] = rRT * RT * uy;
-  c[1][2] = rRT * RT * ux;
-  c[2][2] = rRT * RT * (E + R(2) * RT);
-  pops9(c, ux, uy, h);
+  (void)heq_mode;
+  // raw moments M00 = E, M20 = M02 = S2, M22 = S22 (odd ones zero) through Eq. (3)
+  s[0] = q.rho * (q.E - R(2) * q.S2 + q.S22);
+  s[1] = s[2] = s[3] = s[4] = R(0.5) * q.rho * (q.S2 - q.S22);
+  s[5] = s[6] = s[7] = s[8] = R(0.25) * q.rho * q.S22;
+}
+
+// Central moments about u of the density reference: rho_r m_i(ux) m_j(uy).
+template <class R>
+TC_HD void ref_central(const RowRef<R> &q, R ux, R uy, R k[3][3]) {
+  const R mx[3] = {R(1), -ux, q.th + ux * ux};
+  const R my[3] = {R(1), -uy, q.th + uy * uy};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) k[i][j] = q.rho * mx[i] * my[j];
 }
 
 template <class R>
 struct Consts {
-  R R_, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, inv_bR2;
+  R R_, T0, b, w1, w2, w3, w4, wh, inv_tau_hf;
   int thermal, correction, heq_mode, h_coll;
+  R two_b, inv_RT0;  // 2/b and 1/(R T0)
 };
 
+// 1/x: IEEE division in FP64; in FP32 on the GPU the hardware reciprocal
+// refined by one Newton step (within an ulp or so, no division sequence).
+TC_HD double recip(double x) { return 1.0 / x; }
+TC_HD float recip(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float r = __builtin_amdgcn_rcpf(x);
+  return r * (2.0f - x * r);
+#else
+  return 1.0f / x;
+#endif
+}
+
+// Macroscopic state of a node (Eq. (20), the temperature of Section 4), with
+// the deviations from the row reference kept separately.
 template <class R>
 struct Macro {
-  R rho, ux, uy, T;
+  R drho, rho, ux, uy, dth, th;  // th = R T
+  R sg;                          // sum of g = rho E - rho_r E_r
 };
 
-// Eq. (20) and the temperature of Section 4 from the transformed DFs.
 template <class R>
-TC_HD Macro<R> macros(const Consts<R> &c, const R *f, const R *h, R ax, R ay) {
+TC_HD Macro<R> macros(const Consts<R> &c, const RowRef<R> &q, const R *d, const R *g, R ax, R ay) {
   Macro<R> m;
-  R rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  R jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
-  R ir = R(1) / rho;
-  m.rho = rho;
+  m.drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  m.rho = q.rho + m.drho;
+  const R jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  const R jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+  const R ir = recip(m.rho);
   m.ux = jx * ir + R(0.5) * ax;
   m.uy = jy * ir + R(0.5) * ay;
   if (c.thermal) {
-    R hs = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-    m.T = c.inv_bR2 * (hs * ir - R(0.5) * (m.ux * m.ux + m.uy * m.uy));
+    m.sg = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+    // theta - theta_r = (2/b) ((sum g - drho E_r)/rho - u^2/2)
+    m.dth = c.two_b * ((m.sg - m.drho * q.E) * ir - R(0.5) * (m.ux * m.ux + m.uy * m.uy));
   } else {
-    m.T = c.T0;
+    m.sg = R(0);
+    m.dth = c.R_ * c.T0 - q.th;
   }
+  m.th = q.th + m.dth;
   return m;
 }
 
-// One node's collision.  Inputs: transformed DFs fbar, hbar before collision,
-// their macroscopic values, Dx = d/dx[u_x(1-theta)], Dy = d/dy[u_y(1-theta)]
-// and the node acceleration.  Outputs what streams: P = fbar* + S + C
-// (Eq. (27)) and Q = the updated hbar.
+// Deviation of the density equilibrium at (rho, u, th) from the reference r:
+// central moments of f^eq about its own u are rho (1, 0, th) x (1, 0, th).
 template <class R>
-TC_HD void collide(const Consts<R> &c, const R *f, const R *h, const Macro<R> &m, R Dx, R Dy, R ax, R ay,
-                   R *P, R *Q) {
-  const R rho = m.rho, ux = m.ux, uy = m.uy;
-  const R RT = c.R_ * m.T;
+TC_HD void feq_dev(const RowRef<R> &q, R drho, R ux, R uy, R dth, R *out) {
+  const R rho = q.rho + drho, th = q.th + dth;
+  const R dP = drho * th + q.rho * dth;                   // rho th - rho_r th_r
+  const R dP2 = drho * th * th + q.rho * dth * (th + q.th);  // rho th^2 - rho_r th_r^2
+  const R rr = q.rho, u2 = ux * ux + uy * uy;
+  R c[3][3];
+  c[0][0] = drho;
+  c[1][0] = rr * ux;
+  c[0][1] = rr * uy;
+  c[1][1] = -rr * ux * uy;
+  c[2][0] = dP - rr * ux * ux;
+  c[0][2] = dP - rr * uy * uy;
+  c[2][1] = rr * (q.th + ux * ux) * uy;
+  c[1][2] = rr * (q.th + uy * uy) * ux;
+  c[2][2] = dP2 - rr * (q.th * u2 + ux * ux * uy * uy);
+  (void)rho;
+  pops9(c, ux, uy, out);
+}
+
+// Deviation of the energy equilibrium from the reference s, E = (b th + u^2)/2.
+// mode 0: central moments about u of the continuous total-energy density
+//   (rho E, rho th u, rho th (E + th) on both axes, rho th^2 u_y, rho th^2 u_x,
+//    rho th^2 (E + 2 th)); mode 1: the explicit form of Section 4 (higher raw
+//   moments zero).  sg = rho E - rho_r E_r (the deviation of the total energy).
+template <class R>
+TC_HD void heq_dev(const Consts<R> &c, const RowRef<R> &q, R drho, R ux, R uy, R dth, R sg, R *out) {
+  const R rho = q.rho + drho, th = q.th + dth;
+  const R rr = q.rho, rE = rr * q.E, rS2 = rr * q.S2;
+  const R ux2 = ux * ux, uy2 = uy * uy;
+  if (c.heq_mode == 1) {
+    R E = R(0.5) * (c.b * th + ux2 + uy2);
+    R A = E + th, B = E + R(2) * th, C = th * A, u2 = ux2 + uy2;
+    R hx = R(0.5) * rho, hq = R(0.25) * rho * B * ux * uy;
+    R s0 = rr * (q.E - R(2) * q.S2), s1 = R(0.5) * rr * q.S2;
+    out[0] = rho * (E - B * u2 - R(2) * C) - s0;
+    R sx = B * ux2 + C, sy = B * uy2 + C;
+    out[1] = hx * (A * ux + sx) - s1;
+    out[3] = hx * (-A * ux + sx) - s1;
+    out[2] = hx * (A * uy + sy) - s1;
+    out[4] = hx * (-A * uy + sy) - s1;
+    out[5] = hq;
+    out[6] = -hq;
+    out[7] = hq;
+    out[8] = -hq;
+    return;
+  }
+  const R dP2 = drho * th * th + rr * dth * (th + q.th);
+  const R A = rE * dth + th * sg + dP2;  // rho th (E+th) - rho_r th_r (E_r+th_r)
+  const R rth2 = rho * th * th;
+  const R B = rE * dth * (th + q.th) + th * th * sg +
+              R(2) * (drho * th * th * th + rr * dth * (th * th + th * q.th + q.th * q.th));
+  R h[3][3];
+  h[0][0] = sg;
+  h[1][0] = ux * (rho * th + rE);
+  h[0][1] = uy * (rho * th + rE);
+  h[1][1] = -ux * uy * rE;
+  h[2][0] = A - ux2 * rE;
+  h[0][2] = A - uy2 * rE;
+  h[2][1] = uy * (rth2 + rS2 + ux2 * rE);
+  h[1][2] = ux * (rth2 + rS2 + uy2 * rE);
+  h[2][2] = B - (ux2 + uy2) * rS2 - ux2 * uy2 * rE;
+  pops9(h, ux, uy, out);
+}
+
+// One node's collision in deviation form.  Inputs: d, g before collision, the
+// node's macroscopic state, Dx = d/dx[u_x(1-theta)], Dy = d/dy[u_y(1-theta)],
+// the node acceleration.  Outputs the deviations (from the same row
+// reference) of what streams: P = fbar* + S + C (Eq. (27)) and Q = updated hbar.
+template <class R>
+TC_HD void collide(const Consts<R> &c, const RowRef<R> &q, const R *d, const R *g, const Macro<R> &m, R Dx, R Dy,
+                   R ax, R ay, R *P, R *Q) {
+  const R rho = m.rho, ux = m.ux, uy = m.uy, th = m.th;
+  const R rr = q.rho, ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2;
   if (!(c.correction && c.thermal)) {
     Dx = R(0);
     Dy = R(0);
   }
-  R k[3][3];
-  central9(f, ux, uy, k);
+  R kd[3][3], kr[3][3];
+  central9(d, ux, uy, kd);
+  ref_central(q, ux, uy, kr);
 
-  // Eq. (8) on the trace / normal difference / off-diagonal / 3rd / 4th order
-  // central moments, towards the equilibria of the transformed DF (Section 4).
-  const R Et = k[2][0] + k[0][2], Nt = k[2][0] - k[0][2];
+  const R dP = m.drho * th + rr * m.dth;                      // rho th - rho_r th_r
+  const R dP2 = m.drho * th * th + rr * m.dth * (th + q.th);  // rho th^2 - rho_r th_r^2
   const R rDx = rho * Dx, rDy = rho * Dy;
-  const R Es = (R(1) - c.w2) * Et + c.w2 * (R(2) * rho * RT - R(0.5) * (rDx + rDy));
-  const R Ns = (R(1) - c.w1) * Nt + c.w1 * (R(0.5) * (rDy - rDx));
-  const R ccorr = rho * (uy * uy * Dx + ux * ux * Dy);  // 4th central moment of C is -ccorr
-  R q[3][3];
-  q[0][0] = rho;
-  q[1][0] = R(0.5) * rho * ax;  // -rho a/2 (fbar*) + rho a (S)
-  q[0][1] = R(0.5) * rho * ay;
-  q[1][1] = (R(1) - c.w1) * k[1][1];
-  q[2][0] = R(0.5) * (Es + Ns) + rDx;  // + C
-  q[0][2] = R(0.5) * (Es - Ns) + rDy;
-  q[2][1] = (R(1) - c.w3) * k[2][1];
-  q[1][2] = (R(1) - c.w3) * k[1][2];
-  q[2][2] = (R(1) - c.w4) * k[2][2] + c.w4 * rho * RT * RT - ccorr;
-  pops9(q, ux, uy, P);
+  const R ccorr = rho * (uy2 * Dx + ux2 * Dy);  // 4th central moment of C is -ccorr
+
+  // Eq. (8) towards the equilibria of the transformed DF (Section 4), written
+  // as deviations from the reference's central moments.
+  const R dE = kd[2][0] + kd[0][2], dN = kd[2][0] - kd[0][2];
+  const R dEs = (R(1) - c.w2) * dE + c.w2 * (R(2) * dP - rr * u2 - R(0.5) * (rDx + rDy));
+  const R dNs = (R(1) - c.w1) * dN + c.w1 * (R(0.5) * (rDy - rDx) - rr * (ux2 - uy2));
+  R qd[3][3];
+  qd[0][0] = m.drho;
+  qd[1][0] = R(0.5) * rho * ax + rr * ux;  // (-rho a/2 + rho a) - kr10
+  qd[0][1] = R(0.5) * rho * ay + rr * uy;
+  qd[1][1] = (R(1) - c.w1) * kd[1][1] - c.w1 * kr[1][1];
+  qd[2][0] = R(0.5) * (dEs + dNs) + rDx;  // + C
+  qd[0][2] = R(0.5) * (dEs - dNs) + rDy;
+  qd[2][1] = (R(1) - c.w3) * kd[2][1] - c.w3 * kr[2][1];
+  qd[1][2] = (R(1) - c.w3) * kd[1][2] - c.w3 * kr[1][2];
+  qd[2][2] = (R(1) - c.w4) * kd[2][2] + c.w4 * (dP2 - rr * (q.th * u2 + ux2 * uy2)) - ccorr;
+  pops9(qd, ux, uy, P);
 
   if (!c.thermal) return;
 
   // f - f^eq with f = fbar + S/2 + C/2: central moments, then populations.
-  R d[3][3];
-  d[0][0] = R(0);
-  d[1][0] = R(0);
-  d[0][1] = R(0);
-  d[1][1] = k[1][1];
-  d[2][0] = k[2][0] + R(0.5) * rDx - rho * RT;
-  d[0][2] = k[0][2] + R(0.5) * rDy - rho * RT;
-  d[2][1] = k[2][1];
-  d[1][2] = k[1][2];
-  d[2][2] = k[2][2] - R(0.5) * ccorr - rho * RT * RT;
+  R dd[3][3];
+  dd[0][0] = R(0);
+  dd[1][0] = R(0);
+  dd[0][1] = R(0);
+  dd[1][1] = kd[1][1] + kr[1][1];
+  dd[2][0] = kd[2][0] + R(0.5) * rDx - dP + rr * ux2;
+  dd[0][2] = kd[0][2] + R(0.5) * rDy - dP + rr * uy2;
+  dd[2][1] = kd[2][1] + kr[2][1];
+  dd[1][2] = kd[1][2] + kr[1][2];
+  dd[2][2] = kd[2][2] - R(0.5) * ccorr - (dP2 - rr * (q.th * u2 + ux2 * uy2));
   R dl[9];
-  pops9(d, ux, uy, dl);
+  pops9(dd, ux, uy, dl);
 
-  R he[9];
-  heq9(rho, ux, uy, RT, c.b, c.heq_mode, he);
+  R he[9];  // h^eq - s
+  heq_dev(c, q, m.drho, ux, uy, m.dth, m.sg, he);
 
   // K_a = Z_a/tau_hf (f_a - f_a^eq), Z_a = e_a.u - u^2/2 (Eq. (22))
-  const R hu2 = R(0.5) * (ux * ux + uy * uy);
+  const R hu2 = R(0.5) * u2;
   R K[9];
   K[0] = -hu2 * dl[0];
   K[1] = (ux - hu2) * dl[1];
@@ -229,24 +315,24 @@ TC_HD void collide(const Consts<R> &c, const R *f, const R *h, const Macro<R> &m
     // BGK update of the transformed energy DF (Section 4)
     const R kk = R(1) - R(0.5) * c.wh;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Q[a] = h[a] - c.wh * (h[a] - he[a]) + kk * K[a];
+    for (int a = 0; a < 9; ++a) Q[a] = g[a] - c.wh * (g[a] - he[a]) + kk * K[a];
     return;
   }
   // Two-rate update: energy-flux moments relax with w_h, all others with 1.
   // In populations: Q = h^eq + K/2 + (1 - w_h)/2 e_a.G on the axis links,
-  // G = sum_a (hbar_a - h^eq_a + K_a/2) e_a.
+  // G = sum_a (hbar_a - h^eq_a + K_a/2) e_a (the reference has no flux).
   R n[9];
 #pragma unroll
-  for (int a = 0; a < 9; ++a) n[a] = h[a] - he[a] + R(0.5) * K[a];
+  for (int a = 0; a < 9; ++a) n[a] = g[a] - he[a] + R(0.5) * K[a];
   const R Gx = (n[1] - n[3]) + (n[5] - n[6]) + (n[8] - n[7]);
   const R Gy = (n[2] - n[4]) + (n[5] - n[7]) + (n[6] - n[8]);
-  const R g = R(0.5) * (R(1) - c.wh);
+  const R gg = R(0.5) * (R(1) - c.wh);
 #pragma unroll
   for (int a = 0; a < 9; ++a) Q[a] = he[a] + R(0.5) * K[a];
-  Q[1] += g * Gx;
-  Q[3] -= g * Gx;
-  Q[2] += g * Gy;
-  Q[4] -= g * Gy;
+  Q[1] += gg * Gx;
+  Q[3] -= gg * Gx;
+  Q[2] += gg * Gy;
+  Q[4] -= gg * Gy;
 }
 
 // Force source S (Section 3) as populations: its only non-zero central moments

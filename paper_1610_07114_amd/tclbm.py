@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the method runs in the HIP kernels.
 PyTorch supplies the device memory (a uint8 tensor of tclbm_state_bytes bytes)
-and the stream (the current torch stream of the device).  If the library is
+and the stream (a torch stream per lattice).  If the library is
 missing this module raises at import; there is no fallback.
 """
 from __future__ import annotations
@@ -33,6 +33,8 @@ class tclbm_params(ctypes.Structure):
         ("thermal", ctypes.c_int32), ("correction", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("wall_rho", ctypes.c_int32), ("heq_moments", ctypes.c_int32), ("h_collision", ctypes.c_int32),
         ("accel_field", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("wall_ux", ctypes.c_double * 4), ("wall_uy", ctypes.c_double * 4), ("wall_T", ctypes.c_double * 4),
     ]
 
 
@@ -49,7 +51,9 @@ class tclbm_sums(ctypes.Structure):
 
 EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_set_bc", "tclbm_step",
            "tclbm_step_timed", "tclbm_moments", "tclbm_steps_done", "tclbm_read_state", "tclbm_set_tuning",
-           "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy"]
+           "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
+           "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
+           "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_destroy"]
 
 
 def _load():
@@ -92,6 +96,20 @@ def _load():
     lib.tclbm_last_error.restype = ctypes.c_char_p
     lib.tclbm_hbm_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     lib.tclbm_hbm_copy.restype = ctypes.c_int
+    lib.tclbm_batch_create.argtypes = [ctypes.POINTER(H), ctypes.c_int32, ctypes.POINTER(H)]
+    lib.tclbm_batch_create.restype = ctypes.c_int
+    lib.tclbm_batch_step.argtypes = [H, ctypes.c_int64]
+    lib.tclbm_batch_step.restype = ctypes.c_int
+    lib.tclbm_batch_step_timed.argtypes = [H, ctypes.c_int64, d]
+    lib.tclbm_batch_step_timed.restype = ctypes.c_int
+    lib.tclbm_batch_size.argtypes = [H]
+    lib.tclbm_batch_size.restype = ctypes.c_int32
+    lib.tclbm_batch_waves.argtypes = [H]
+    lib.tclbm_batch_waves.restype = ctypes.c_int64
+    lib.tclbm_batch_set_graph_chunk.argtypes = [H, ctypes.c_int32]
+    lib.tclbm_batch_set_graph_chunk.restype = ctypes.c_int
+    lib.tclbm_batch_destroy.argtypes = [H]
+    lib.tclbm_batch_destroy.restype = ctypes.c_int
     return lib
 
 
@@ -184,7 +202,40 @@ def tclbm_hbm_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int):
     _chk(_lib.tclbm_hbm_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes, ctypes.c_void_p(stream)))
 
 
-# ---- convenience wrapper --------------------------------------------------------------
+def tclbm_batch_create(handles) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    b = ctypes.c_void_p()
+    _chk(_lib.tclbm_batch_create(arr, len(handles), ctypes.byref(b)))
+    return b
+
+
+def tclbm_batch_step(b, n: int):
+    _chk(_lib.tclbm_batch_step(b, int(n)))
+
+
+def tclbm_batch_step_timed(b, n: int) -> float:
+    ms = ctypes.c_double()
+    _chk(_lib.tclbm_batch_step_timed(b, int(n), ctypes.byref(ms)))
+    return ms.value
+
+
+def tclbm_batch_size(b) -> int:
+    return int(_lib.tclbm_batch_size(b))
+
+
+def tclbm_batch_waves(b) -> int:
+    return int(_lib.tclbm_batch_waves(b))
+
+
+def tclbm_batch_set_graph_chunk(b, chunk: int):
+    _chk(_lib.tclbm_batch_set_graph_chunk(b, int(chunk)))
+
+
+def tclbm_batch_destroy(b):
+    _chk(_lib.tclbm_batch_destroy(b))
+
+
+# ---- convenience wrappers ------------------------------------------------------------
 
 class Lattice:
     """One lattice resident on a GPU.  `case` is a workloads.Case."""
@@ -197,6 +248,11 @@ class Lattice:
             setattr(p, name, getattr(case, name))
         p.storage = STORE[storage]
         p.accel_field = 1 if case.ax_field is not None else 0
+        for side in range(4):
+            p.bc[side] = int(case.bc[side])
+            p.wall_ux[side] = float(case.wall_ux[side])
+            p.wall_uy[side] = float(case.wall_uy[side])
+            p.wall_T[side] = float(case.wall_T[side])
         for k, v in over.items():
             setattr(p, k, v)
         self.params = p
@@ -205,13 +261,11 @@ class Lattice:
             raise TclbmError(E_INVALID, "invalid parameters")
         self.device = torch.device(device)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the legacy default stream
+        # cannot be captured into HIP graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.h = tclbm_create(p, self.buf.data_ptr(), self.nbytes, self.stream.cuda_stream, case.rho, case.ux,
                               case.uy, case.T if case.T is not None else case.rho, case.ax_field, case.ay_field)
-        for side in range(4):
-            kind = case.bc[side]
-            if kind != PERIODIC:
-                tclbm_set_bc(self.h, side, kind, case.wall_ux[side], case.wall_uy[side], case.wall_T[side])
 
     def step(self, n: int = 1) -> "Lattice":
         tclbm_step(self.h, n)
@@ -239,6 +293,40 @@ class Lattice:
             tclbm_destroy(self.h)
             self.h = None
             self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lattices advanced together, one kernel launch per step.  All members
+    must share the storage form and the stream."""
+
+    def __init__(self, lattices):
+        self.members = list(lattices)
+        self.h = tclbm_batch_create([m.h for m in self.members])
+
+    def step(self, n: int = 1) -> "Batch":
+        tclbm_batch_step(self.h, n)
+        return self
+
+    def step_timed(self, n: int) -> float:
+        return tclbm_batch_step_timed(self.h, n)
+
+    @property
+    def waves(self) -> int:
+        return tclbm_batch_waves(self.h)
+
+    def set_graph_chunk(self, chunk: int):
+        tclbm_batch_set_graph_chunk(self.h, chunk)
+
+    def close(self):
+        if self.h is not None:
+            tclbm_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

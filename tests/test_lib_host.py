@@ -56,10 +56,15 @@ def test_state_bytes_plan(T):
 
 @pytest.mark.parametrize("field,value", [("nx", 2), ("ny", 0), ("tau_f", 0.5), ("gamma", 1.0), ("Pr", 0.0),
                                          ("w2", 2.0), ("w3", 0.0), ("storage", 7), ("R", 0.5),
-                                         ("wall_rho", 3), ("h_collision", 2), ("thermal", 2)])
+                                         ("wall_rho", 3), ("h_collision", 2), ("thermal", 2),
+                                         ("bc", (2, 2, 0, 0)), ("bc", (1, 0, 0, 0)), ("bc", (0, 0, 2, 0))])
 def test_invalid_parameters_rejected(T, field, value):
     p = T.tclbm_default_params(16, 16)
-    setattr(p, field, value)
+    if field == "bc":
+        for i, v in enumerate(value):
+            p.bc[i] = v
+    else:
+        setattr(p, field, value)
     assert T.tclbm_state_bytes(p) == 0
     h = ctypes.c_void_p()
     n = 256
@@ -108,16 +113,16 @@ def shim(tmp_path_factory):
                            os.path.join(ROOT, "tests", "node_shim.cpp")])
     L = ctypes.CDLL(out)
     d = ctypes.POINTER(ctypes.c_double)
-    L.shim_macros.argtypes = [d, d, d, ctypes.c_double, ctypes.c_double, d]
+    L.shim_macros.argtypes = [d, d, d, d, ctypes.c_double, ctypes.c_double, d]
     L.shim_collide.argtypes = [d, d, d, d] + [ctypes.c_double] * 4 + [d, d]
+    L.shim_feq.argtypes = [d, d] + [ctypes.c_double] * 4 + [d]
+    L.shim_heq.argtypes = [d, d] + [ctypes.c_double] * 4 + [d]
     return L
 
 
-@pytest.mark.parametrize("seed", range(40))
-def test_kernel_node_math_matches_oracle_fp64(shim, seed):
+def _node_case(seed):
     import oracle as O
     from helpers import random_pops
-    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     rng = np.random.default_rng(seed)
     tau = rng.uniform(0.52, 1.5)
     w2, w3, w4 = rng.uniform(0.3, 1.9, 3)
@@ -129,17 +134,42 @@ def test_kernel_node_math_matches_oracle_fp64(shim, seed):
                  thermal=th)
     b, R, w1 = 2 / (g - 1), 1 / 3, 1 / tau
     wh = 1 / ((tau - 0.5) / Pr + 0.5)
-    cst = np.array([R, 1.0, b, w1, w2, w3, w4, wh, w1 * (Pr - 1), 2 / (b * R), th, 1, hm, hc])
+    cst = np.array([R, 1.0, b, w1, w2, w3, w4, wh, w1 * (Pr - 1), th, 1, hm, hc])
     fb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4)
     hb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4) * 0.8
+    # a row reference near, not at, the node state (athermal: theta_r = R T0)
+    ref = np.array([rng.uniform(0.8, 1.2), R * (rng.uniform(0.9, 1.1) if th else 1.0)])
+    return O, p, cst, fb, hb, ref, rng
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_kernel_node_math_matches_oracle_fp64(shim, seed):
+    """The kernels' per-node arithmetic (deviation form, central moments in a
+    factored 3-point route) reproduces the oracle's node step in FP64."""
+    O, p, cst, fb, hb, ref, rng = _node_case(seed)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     ax, ay, Dx, Dy = rng.uniform(-0.02, 0.02, 4)
     mo = np.array(O.node_macros(p, fb, hb, ax, ay))
     mg = np.zeros(4)
-    shim.shim_macros(P(cst), P(fb), P(hb), ax, ay, P(mg))
-    np.testing.assert_allclose(mg, mo, rtol=0, atol=1e-15)
+    shim.shim_macros(P(cst), P(ref), P(fb), P(hb), ax, ay, P(mg))
+    np.testing.assert_allclose(mg, mo, rtol=0, atol=2e-15)
     fo, ho = O.collide_node(p, fb, hb, *mo, Dx, Dy, ax, ay)
     Pg, Qg = np.zeros(9), np.zeros(9)
-    shim.shim_collide(P(cst), P(fb), P(hb), P(mo), Dx, Dy, ax, ay, P(Pg), P(Qg))
-    np.testing.assert_allclose(Pg, fo, rtol=0, atol=2e-15)
-    if th:
-        np.testing.assert_allclose(Qg, ho, rtol=0, atol=2e-15)
+    shim.shim_collide(P(cst), P(ref), P(fb), P(hb), Dx, Dy, ax, ay, P(Pg), P(Qg))
+    np.testing.assert_allclose(Pg, fo, rtol=0, atol=3e-15)
+    if p.thermal:
+        np.testing.assert_allclose(Qg, ho, rtol=0, atol=3e-15)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_kernel_equilibria_match_oracle_fp64(shim, seed):
+    O, p, cst, fb, hb, ref, rng = _node_case(100 + seed)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rho, T = rng.uniform(0.7, 1.3), rng.uniform(0.9, 1.1)
+    ux, uy = rng.uniform(-0.1, 0.1, 2)
+    f, h = np.zeros(9), np.zeros(9)
+    shim.shim_feq(P(cst), P(ref), rho, ux, uy, T, P(f))
+    np.testing.assert_allclose(f, O.feq(rho, ux, uy, T / 3), atol=2e-15)
+    if p.thermal:  # no energy DF in the athermal scheme
+        shim.shim_heq(P(cst), P(ref), rho, ux, uy, T, P(h))
+        np.testing.assert_allclose(h, O.heq(rho, ux, uy, T / 3, cst[2], int(cst[11])), atol=3e-15)
