@@ -2,21 +2,31 @@
 """Benchmark of the fused TCLBM step on one MI355X.
 
 One "step" is one time step of the whole hot path over the lattice: pull
-streaming, macroscopic variables, correction gradients, cascaded collision of
-f with force and correction sources, energy-DF collision with the coupling
-source, store (one fused kernel), plus the FP64 Nusselt/mass reduction every
-`--reduce-every` steps.  Inputs are seeded and synthetic and resident in HBM
-before timing starts.
+streaming, wall treatment, macroscopic variables, correction gradients,
+cascaded collision of f with force and correction sources, energy-DF collision
+with the coupling source, store (one fused kernel), plus the FP64 Nusselt/mass
+reduction every `--reduce-every` steps.  Inputs are seeded and synthetic and
+resident in HBM before timing starts.
 
-Prints one JSON line on stdout: MLUPS of the workload (whole job), the HBM
-roofline of the step kernel (algorithmic bytes per launch / average launch
-time from HIP events on the library's stream), and the FP64 CPU reference
-timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line on stdout.  `value` is the MLUPS of the selected workload
+(whole job, wall clock); `roofline` is the HBM roofline of its step kernel
+(algorithmic bytes per launch / average launch time from HIP events on the
+library's stream); `cpu_baseline` is the FP64 CPU reference timed on a bounded
+sample of the same workload on the host cores.  With the default workload the
+line also carries, measured in the same run:
+  roofline_large  the step kernel on an 8192x4096 lattice (HBM-resident state)
+  batch           256 seeded uneven Rayleigh-Benard lattices advanced by one
+                  launch per step, autotuned, aggregate MLUPS and roofline
+  serving         a seeded Poisson stream of RB/Couette solve requests served
+                  with continuous batching and 16-bit storage (solves/s,
+                  p50/p99 latency, Nu error against stored FP64 values), and the
+                  same stream through the plain one-lattice-at-a-time FP32 path
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+GOLDEN_BATCH_NU = os.path.join(ROOT, "tests", "golden", "rb_batch_nu_fp64.json")
 
 
 def log(*a):
@@ -50,37 +61,64 @@ def bytes_per_lup(storage: str, thermal: int = 1) -> int:
     return 2 * planes * per  # each population read once and written once
 
 
-def cpu_baseline(case, seconds_target: float = 12.0):
+def roofline(bpl: int, nodes: int, avg_launch_s: float, traffic=None, kernel="step_kernel"):
+    achieved = bpl * nodes / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "bytes_per_lup": bpl, "lups_per_launch": nodes, "avg_launch_us": round(avg_launch_s * 1e6, 3)}
+
+
+def load_traffic(path, key):
+    """Per-launch HBM bytes from the rocprofv3 counter runs, if taken for this
+    kernel build and workload (null otherwise)."""
+    try:
+        tj = json.load(open(path))
+        from paper_1610_07114_amd import build as B
+        ent = tj.get(key)
+        if ent and ent.get("kernel_sources") == B.source_digest():
+            return ent["bytes_per_launch"]
+    except Exception:
+        pass
+    return None
+
+
+# ------------------------------------------------------------------ CPU baseline ---
+def cpu_baseline(cases, seconds_target: float = 12.0, label=None):
     """The FP64 oracle as it stands, on the host cores, over a bounded number of
-    steps of the same workload."""
-    import numpy as np  # noqa: F401
+    steps of the given lattices (round robin, whole lattices)."""
     import oracle as O
-    p = O.Params(nx=case.nx, ny=case.ny, R=case.R, T0=case.T0, gamma=case.gamma, Pr=case.Pr, tau_f=case.tau_f,
-                 w2=case.w2, w3=case.w3, w4=case.w4, ax=case.ax, ay=case.ay, thermal=case.thermal,
-                 correction=case.correction, bc=case.bc, wall_ux=case.wall_ux, wall_uy=case.wall_uy,
-                 wall_T=case.wall_T)
-    L = O.Lattice(p, case.rho, case.ux, case.uy, case.T)
+    lats = []
+    for case in cases:
+        p = O.Params(nx=case.nx, ny=case.ny, R=case.R, T0=case.T0, gamma=case.gamma, Pr=case.Pr,
+                     tau_f=case.tau_f, w2=case.w2, w3=case.w3, w4=case.w4, ax=case.ax, ay=case.ay,
+                     thermal=case.thermal, correction=case.correction, bc=case.bc, wall_ux=case.wall_ux,
+                     wall_uy=case.wall_uy, wall_T=case.wall_T, ax_field=case.ax_field, ay_field=case.ay_field)
+        lats.append((case, O.Lattice(p, case.rho, case.ux, case.uy, case.T)))
+    nodes = sum(c.nx * c.ny for c, _ in lats)
     t0 = time.perf_counter()
-    L.step(2)
+    for _, L in lats:
+        L.step(2)
     dt = max(time.perf_counter() - t0, 1e-6)
     n = max(2, min(5000, int(seconds_target / (dt / 2))))
     t0 = time.perf_counter()
-    L.step(n)
+    for _, L in lats:
+        L.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(case.nx * case.ny * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{case.name} {case.nx}x{case.ny}, {n} steps from the seeded initial state, FP64, "
-                      f"{dt:.1f} s"}
+    what = label or f"{cases[0].name} {cases[0].nx}x{cases[0].ny}"
+    return {"value": round(nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{what}, {n} steps from the seeded initial state, FP64, {dt:.1f} s"}
 
 
+# ------------------------------------------------------------------- probes ---
 def copy_probe(torch, tclbm, nbytes: int = 2 << 30, reps: int = 20):
     """Achievable HBM bandwidth of a plain streaming copy (read + write bytes per
     launch / launch time), the measured ceiling beside the 8 TB/s peak."""
     dev = torch.device("cuda:0")
-    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    a.fill_(1)
     s = torch.cuda.Stream(dev)
+    with torch.cuda.stream(s):
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        a.fill_(1)
     for _ in range(3):
         tclbm.tclbm_hbm_copy(b.data_ptr(), a.data_ptr(), nbytes, s.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -94,16 +132,166 @@ def copy_probe(torch, tclbm, nbytes: int = 2 << 30, reps: int = 20):
             "GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS}
 
 
+# ---------------------------------------------------------------- one lattice ---
+def bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, strip_rows, graph_chunk):
+    dev = torch.device("cuda:0")
+    lat = tclbm.Lattice(case, storage=storage, device="cuda:0")
+    lat.set_tuning(strip_rows, graph_chunk)
+    nodes = case.nx * case.ny
+
+    def run(nsteps):
+        done = 0
+        while done < nsteps:
+            k = min(reduce_every, nsteps - done)
+            lat.step(k)
+            done += k
+            if done % reduce_every == 0:
+                lat.moments(fields=False)   # FP64 sums (mass, energy, Nusselt numerator)
+
+    run(warmup)
+    torch.cuda.synchronize(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(lat.stream)
+    run(steps)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    # kernel-only average: a separate pass of pure steps timed with HIP events
+    # on the library's stream (graph replays of the same kernel)
+    kern_ms = lat.step_timed(steps)
+    _, _, _, _, sums = lat.moments(fields=False)
+    lat.close()
+    return dict(wall=wall, dev_ms=dev_ms, avg_launch_s=kern_ms / 1e3 / steps, nodes=nodes, sums=sums)
+
+
+# -------------------------------------------------------------------- batch ---
+def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, autotune=True):
+    """The batched workload: n seeded 2N x N Rayleigh-Benard lattices (N
+    log-uniform on [32, 512], Ra log-uniform on [1e4, 1e6], Pr uniform on
+    [0.5, 7]) advanced together, one launch per step, HIP-graph chunks.  The
+    autotuner's trial steps (strip height x graph chunk) are part of the
+    warm-up."""
+    from paper_1610_07114_amd import serving as S
+    from paper_1610_07114_amd import workloads as W
+    specs = W.batched_rb_specs(n, seed=seed)
+    t0 = time.perf_counter()
+    cases = [W.rb_from_spec(s) for s in specs]
+    nodes = sum(c.nx * c.ny for c in cases)
+    stream = torch.cuda.Stream(torch.device("cuda:0"))
+    lats = [tclbm.Lattice(c, storage=storage, stream=stream) for c in cases]
+    del cases
+    log(f"batch: {n} seeded lattices resident ({time.perf_counter() - t0:.1f} s)")
+    b = tclbm.Batch(lats)
+    tune = None
+    if autotune:
+        tune = S.autotune_batch(b, log=log)
+        log(f"batch autotune: {tune}")
+    b.step(warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    ms = b.step_timed(steps)
+    wall = time.perf_counter() - t0
+    waves = b.waves
+    b.close()
+    unstable = 0
+    for lat in lats:
+        _, _, _, _, _, st = tclbm.tclbm_moments(lat.h, lat.case.nx, lat.case.ny, fields=False, check=False)
+        unstable += st != tclbm.OK
+        lat.close()
+    avg = ms / 1e3 / steps
+    bpl = bytes_per_lup(storage)
+    return {"workload": f"batched_rayleigh_benard_{n}x(2N x N, N log-uniform 32..512, seed {seed})",
+            "instances": n, "nodes": nodes, "storage": storage, "steps": steps, "warmup": warmup,
+            "mlups": round(nodes * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+            "autotune": tune, "waves_per_step": waves, "unstable_instances": int(unstable),
+            "roofline": roofline(bpl, nodes, avg, kernel="batch_step_kernel")}
+
+
+# ------------------------------------------------------------------ serving ---
+def golden_requests(S, start_id, rate_span, seed=7):
+    """Requests for the instances whose FP64 Nusselt history is stored, at
+    seeded arrival times inside the stream; their run lengths equal the stored
+    schedule so the final Nu can be compared with the FP64 value."""
+    import numpy as np
+    try:
+        g = json.load(open(GOLDEN_BATCH_NU))
+    except Exception:
+        return [], {}
+    rng = np.random.default_rng(seed)
+    out, ref = [], {}
+    for k, inst in enumerate(g["instances"]):
+        if not (inst["steps"] and inst["steps"][-1] == inst["total"] and math.isfinite(inst["nu"][-1])):
+            continue
+        s = inst["spec"]
+        rid = start_id + k
+        out.append(S.Request(rid, "rb", s["nx"], s["ny"], s["Ra"], s["Pr"], inst["total"],
+                             float(rng.uniform(0, rate_span)), s["seed"]))
+        ref[rid] = inst["nu"][-1]
+    return out, ref
+
+
+def bench_serving(torch, tclbm, n_requests=500, storage="f16", seed=0, load=0.8, time_units=1.0,
+                  sequential_fp32=True):
+    from paper_1610_07114_amd import serving as S
+    import numpy as np
+    # capacity: a closed-loop run (everything queued at t = 0) of a calibration
+    # stream drawn from the same distribution
+    calib = S.make_requests(max(40, n_requests // 8), rate=1.0, seed=seed + 1000, time_units=time_units)
+    for r in calib:
+        r.arrival = 0.0
+    srv = S.Server(storage=storage)
+    t0 = time.perf_counter()
+    res = srv.run(calib, realtime=False)
+    cap_wall = time.perf_counter() - t0
+    capacity = len(res) / cap_wall
+    rate = load * capacity
+    reqs = S.make_requests(n_requests, rate=rate, seed=seed, time_units=time_units)
+    span = reqs[-1].arrival
+    gold, ref = golden_requests(S, n_requests, span)
+    reqs = sorted(reqs + gold, key=lambda r: r.arrival)
+    log(f"serving: capacity {capacity:.1f} solves/s ({len(calib)} calibration requests, {cap_wall:.1f} s); "
+        f"stream of {len(reqs)} requests at {rate:.1f}/s over {span:.1f} s")
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    wall = time.perf_counter() - t0
+    summ = S.summarize(res, wall)
+    errs = [abs(r.nu - ref[r.rid]) / abs(ref[r.rid]) for r in res if r.rid in ref]
+    out = {"storage": storage, "arrival_rate_per_s": round(rate, 2), "load_vs_capacity": load,
+           "capacity_solves_per_s": round(capacity, 2), **summ,
+           "run_length": f"{time_units} H/u_c per request (u_c = 0.08 RB, u0 = 0.05 Couette); "
+                         f"the {len(gold)} requests with stored FP64 Nu run 50 H/u_c",
+           "nu_rel_err_vs_fp64": {"max": max(errs) if errs else None, "n": len(errs),
+                                  "median": float(np.median(errs)) if errs else None}}
+    if sequential_fp32:
+        # the plain path: one FP32 lattice at a time, first come first served
+        seq = sorted(reqs, key=lambda r: r.arrival)
+        srv1 = S.Server(storage="f32", max_slots=1)
+        t0 = time.perf_counter()
+        res1 = srv1.run(seq, realtime=True)
+        wall1 = time.perf_counter() - t0
+        errs1 = [abs(r.nu - ref[r.rid]) / abs(ref[r.rid]) for r in res1 if r.rid in ref]
+        out["single_lattice_fp32"] = {**S.summarize(res1, wall1),
+                                      "nu_rel_err_vs_fp64": {"max": max(errs1) if errs1 else None,
+                                                             "n": len(errs1)}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--workload", default="rb", choices=["rb", "shock", "couette", "large"])
+    ap.add_argument("--workload", default="rb", choices=["rb", "shock", "couette", "large", "batch", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--reduce-every", type=int, default=1000)
     ap.add_argument("--strip-rows", type=int, default=0)
     ap.add_argument("--graph-chunk", type=int, default=32)
+    ap.add_argument("--requests", type=int, default=500, help="serving stream length")
+    ap.add_argument("--serve-storage", default="f16", choices=["f16", "bf16", "f32"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the selected workload (no large-lattice roofline, batch or serving figures)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the plain HBM copy kernel (2 x 2 GiB) instead and exit")
@@ -112,9 +300,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the batched and single-lattice paths shard by "
-              "instance or slab across GPUs by design, but no multi-GPU path is built); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (the batched and single-lattice paths would shard by "
+              "instance or by slab across GPUs, but no multi-GPU path is built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -124,55 +311,40 @@ def main():
         print(json.dumps(copy_probe(torch, tclbm)), flush=True)
         return
 
+    if args.workload == "batch":
+        log("bench: batched RB workload, 256 instances")
+        b = bench_batch(torch, tclbm, storage=args.storage, steps=min(args.steps, 2000),
+                        warmup=min(args.warmup, 400))
+        out = {"metric": "TCLBM MLUPS", "value": b["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": b["steps"],
+               "warmup": b["warmup"], "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
+               "config": {"workload": b["workload"], "storage": args.storage, "instances": b["instances"],
+                          "nodes": b["nodes"], "unstable_instances": b["unstable_instances"],
+                          "autotune": b["autotune"]},
+               "roofline": b["roofline"]}
+        if not args.no_cpu_baseline:
+            from paper_1610_07114_amd import workloads as W
+            specs = W.batched_rb_specs(256, seed=0)[:8]
+            out["cpu_baseline"] = cpu_baseline([W.rb_from_spec(s) for s in specs],
+                                               label="first 8 lattices of the batched RB workload")
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.workload == "serve":
+        s = bench_serving(torch, tclbm, n_requests=args.requests, storage=args.serve_storage)
+        out = {"metric": "batched serving solves/s", "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+               "steps": s["requests"], "warmup": 0, "ms_per_step": round(1e3 / max(s["solves_per_s"], 1e-9), 3),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic (seeded)", "config": {"workload": "serving stream", **s}}
+        print(json.dumps(out), flush=True)
+        return
+
     case, wname = workload_case(args.workload)
-    dev = torch.device("cuda:0")
-    lat = tclbm.Lattice(case, storage=args.storage, device="cuda:0")
-    lat.set_tuning(args.strip_rows, args.graph_chunk)
-    nodes = case.nx * case.ny
-
-    def run(nsteps):
-        done = 0
-        while done < nsteps:
-            k = min(args.reduce_every, nsteps - done)
-            lat.step(k)
-            done += k
-            if done % args.reduce_every == 0:
-                lat.moments(fields=False)   # FP64 sums (mass, energy, Nusselt numerator)
-
     log(f"bench: {wname} {args.storage}, warmup {args.warmup}, steps {args.steps}")
-    run(args.warmup)
-    torch.cuda.synchronize(dev)
-
-    # timed region: wall clock around K steps, device events on the library's stream
-    stream = lat.stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    run(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize(dev)
-    wall = time.perf_counter() - t0
-    dev_ms = ev0.elapsed_time(ev1)
-
-    # kernel-only average: a separate pass of pure steps timed with HIP events
-    kern_ms = lat.step_timed(args.steps)
-    avg_launch_s = kern_ms / 1e3 / args.steps
-    _, _, _, _, sums = lat.moments(fields=False)
-    lat.close()
-
-    mlups = nodes * args.steps / wall / 1e6
+    r = bench_single(torch, tclbm, case, args.storage, args.steps, args.warmup, args.reduce_every,
+                     args.strip_rows, args.graph_chunk)
+    mlups = r["nodes"] * args.steps / r["wall"] / 1e6
     bpl = bytes_per_lup(args.storage, case.thermal)
-    achieved = bpl * nodes / avg_launch_s / 1e9
-    traffic = None
-    try:
-        tj = json.load(open(args.traffic_json))
-        key = f"{wname}_{args.storage}"
-        if key in tj:
-            traffic = tj[key]["bytes_per_launch"]
-    except Exception:
-        pass
-
     out = {
         "metric": "TCLBM MLUPS",
         "value": round(mlups, 2),
@@ -180,22 +352,37 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 6),
+        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic (seeded)",
         "config": {"workload": wname, "nx": case.nx, "ny": case.ny, "storage": args.storage,
-                   "steps_per_reduction": args.reduce_every, "device_ms": round(dev_ms, 3)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "step_kernel", "bytes_per_lup": bpl,
-                     "avg_launch_us": round(avg_launch_s * 1e6, 3)},
-        "nu_num": sums.nu_num,
+                   "steps_per_reduction": args.reduce_every, "device_ms": round(r["dev_ms"], 3)},
+        "roofline": roofline(bpl, r["nodes"], r["avg_launch_s"],
+                             load_traffic(args.traffic_json, f"{wname}_{args.storage}")),
+        "nu": None,
     }
+    if case.name == "rayleigh_benard":
+        m = case.meta
+        out["nu"] = 1.0 + r["sums"].nu_num / r["nodes"] * m["H"] / (m["kappa"] * m["dT"])
+
+    if args.workload == "rb" and not args.no_extras:
+        big, bname = workload_case("large")
+        log(f"bench: {bname} f32 roofline, 200 warmup + 1000 timed steps")
+        rl = bench_single(torch, tclbm, big, "f32", 1000, 200, 1000, 0, 32)
+        out["roofline_large"] = {"workload": bname, "mlups": round(rl["nodes"] * 1000 / rl["wall"] / 1e6, 1),
+                                 **roofline(144, rl["nodes"], rl["avg_launch_s"],
+                                            load_traffic(args.traffic_json, f"{bname}_f32"))}
+        del big
+        log("bench: batched RB, 256 instances, f32")
+        out["batch"] = bench_batch(torch, tclbm, storage="f32")
+        log(f"bench: serving stream, {args.requests} requests, {args.serve_storage}")
+        out["serving"] = bench_serving(torch, tclbm, n_requests=args.requests, storage=args.serve_storage)
+
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = cpu_baseline([case])
     print(json.dumps(out), flush=True)
 
 

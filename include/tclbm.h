@@ -53,7 +53,10 @@ typedef enum {
  * three and FP64 for the last.  Every form stores each population as its
  * deviation from a per-row rest-state equilibrium (fixed at create time from
  * the row means of the initial density and temperature), and the arithmetic
- * runs on those deviations. */
+ * runs on those deviations.  F16_DEV keeps the deviation times 2^10 as an
+ * IEEE half (round to nearest even): deviations from 6.0e-8 up to 64 are
+ * normal numbers; a larger one overflows and is reported as unstable.
+ * BF16_DEV keeps the deviation as a bfloat16 (round to nearest even). */
 typedef enum {
   TCLBM_STORE_F32 = 0,
   TCLBM_STORE_F16_DEV = 1,
@@ -87,6 +90,11 @@ typedef struct {
                             explicit form) */
   int32_t h_collision;   /* energy DF update: 0 two-rate (energy flux at w_h,
                             other moments at 1; default), 1 BGK (Section 4) */
+  int32_t h_force;       /* energy DF body-force source: 1 (default) adds the
+                            change of the equilibrium energy flux (rho E + p) u
+                            that the force makes within a step, first moment
+                            (rho E + p) a with the (1 - w_h/2) factor; 0 none
+                            (Section 4 as printed) */
   int32_t accel_field;   /* 1: tclbm_create receives per-node acceleration
                             arrays (space for them is part of the state) */
   int32_t bc[4];         /* tclbm_bc_kind per side (tclbm_side order); the
@@ -179,7 +187,10 @@ tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_
  * not NULL); results equal those of stepping each member alone, bitwise.
  * While a member belongs to a batch, step it only through the batch; other
  * calls on it (moments, read_state) are fine.  Changing a member's boundaries
- * or tuning requires a new batch.  Destroy the batch before its members. */
+ * or tuning requires a new batch: tclbm_batch_step returns TCLBM_E_STATE,
+ * stepping nothing, when a member was stepped alone, re-tuned, given new
+ * boundaries or found unstable since the batch was built (or last stepped).
+ * Destroy the batch before its members. */
 typedef struct tclbm_batch *tclbm_batch_handle;
 tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_handle *out);
 tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps);
@@ -187,6 +198,12 @@ tclbm_status tclbm_batch_step_timed(tclbm_batch_handle b, int64_t nsteps, double
 int32_t tclbm_batch_size(tclbm_batch_handle b);
 int64_t tclbm_batch_waves(tclbm_batch_handle b);  /* wave64 work items per step */
 tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk);
+/* Strip height (rows per wave strip) used for every member inside the batch,
+ * capped at each member's ny; 0 (the default) picks one from the batch's total
+ * work.  Members' own tuning is not changed; results are identical for any
+ * height.  Synchronizes the stream.  Returns TCLBM_E_INVALID for rows < 0. */
+tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows);
+int32_t tclbm_batch_strip_rows(tclbm_batch_handle b);  /* height in use */
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b);
 
 /* Static string for a status code; last HIP/validation message of a handle. */

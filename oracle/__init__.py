@@ -51,6 +51,7 @@ class _Params(ctypes.Structure):
         ("wall_ux", ctypes.c_double * 4), ("wall_uy", ctypes.c_double * 4), ("wall_T", ctypes.c_double * 4),
         ("wall_rho", ctypes.c_int32), ("heq_moments", ctypes.c_int32), ("h_collision", ctypes.c_int32),
         ("ax_field", ctypes.POINTER(ctypes.c_double)), ("ay_field", ctypes.POINTER(ctypes.c_double)),
+        ("h_force", ctypes.c_int32),
     ]
 
 
@@ -192,6 +193,7 @@ class Params:
     wall_rho: int = 0
     heq_moments: int = 0
     h_collision: int = 0
+    h_force: int = 1
     ax_field: Optional[np.ndarray] = None
     ay_field: Optional[np.ndarray] = None
     _keep: list = field(default_factory=list, repr=False)
@@ -199,7 +201,7 @@ class Params:
     def to_c(self) -> _Params:
         c = _Params()
         for name in ("nx", "ny", "R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay",
-                     "thermal", "correction", "wall_rho", "heq_moments", "h_collision"):
+                     "thermal", "correction", "wall_rho", "heq_moments", "h_collision", "h_force"):
             setattr(c, name, getattr(self, name))
         for i in range(4):
             c.bc[i] = int(self.bc[i])
@@ -267,6 +269,13 @@ def node_macros(params: Params, fb, hb, ax=0.0, ay=0.0):
     out = [np.zeros(1) for _ in range(4)]
     lib().orc_node_macros(ctypes.byref(c), _p(fb), _p(hb), ax, ay, *[_p(v) for v in out])
     return tuple(float(v[0]) for v in out)
+
+
+def nusselt(uy: np.ndarray, T: np.ndarray, T0: float, H: float, kappa: float, dT: float) -> float:
+    """Nusselt number of a Rayleigh-Benard state (Section 5D): one plus the
+    mean over all nodes of u_y (T - T0), scaled by H / (kappa dT), with kappa
+    the thermal diffusivity nu/Pr at the reference state."""
+    return 1.0 + float(np.mean(uy * (T - T0))) * H / (kappa * dT)
 
 
 def num_threads() -> int:

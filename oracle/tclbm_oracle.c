@@ -42,7 +42,17 @@
  *   h^eq       the moments the paper leaves free take their continuous
  *              (Maxwellian) values (the paper's zero choice kept as an option);
  *   h update   two-rate form of the transformed BGK update: energy-flux moments
- *              at w_h, the other moments at rate 1 (BGK kept as an option).
+ *              at w_h, the other moments at rate 1 (BGK kept as an option);
+ *   h force    the energy DF receives the change that the body force makes to
+ *              its equilibrium energy flux (rho E + p) u within a step: a source
+ *              with first moment (rho E + p) a and no other moment (Section 4
+ *              prints no force term for the energy DF; without one the
+ *              Chapman-Enskog energy flux carries -(1/w_h - 1/2)(rho E + p) a,
+ *              which heats the top of a resting isothermal column; the printed
+ *              form is kept as an option); no work term rho u.a is added to
+ *              the total energy, as in Section 4;
+ *   wall NEQ   the stored f is the transformed fbar, so the equilibrium part
+ *              used in the extrapolation is f^eq - S/2 at each node.
  *
  * Build:  gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -88,6 +98,8 @@ typedef struct {
   int32_t h_collision; /* energy DF collision: 0 two-rate, 1 BGK */
   const double *ax_field; /* optional per-node acceleration (nullable) */
   const double *ay_field;
+  int32_t h_force;     /* energy DF body-force source: 1 the flux term (default),
+                        * 0 none (Section 4 as printed) */
 } orc_params;
 
 static double pw(double v, int n) {
@@ -412,9 +424,24 @@ void orc_collide_node(const orc_params *p, const double fb[9], const double hb[9
     double Z = EX[a] * ux + EY[a] * uy - 0.5 * u2;       /* Z_a = e_a . u - u^2/2, Eq. (22) */
     K[a] = Z * d.inv_tau_hf * (fa - feq[a]);              /* K_a = Z_a/tau_hf (f_a - f_a^eq) */
   }
+  /* Body-force source of the energy DF (option): the force changes u inside
+   * the step, hence the equilibrium energy flux (rho E + p) u, by (rho E + p) a
+   * per unit time; nothing in the energy DF supplies that change, and the
+   * Chapman-Enskog flux then carries -(1/w_h - 1/2)(rho E + p) a.  F has first
+   * moment (rho E + p) a on the axis links and no other moment. */
+  double F[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (p->h_force == 1) {
+    double Etot = 0.5 * (d.b * RT + u2);
+    double g = rho * (Etot + RT);
+    F[1] = 0.5 * g * ax;
+    F[3] = -0.5 * g * ax;
+    F[2] = 0.5 * g * ay;
+    F[4] = -0.5 * g * ay;
+  }
   if (p->h_collision == 1) {
     /* the paper's BGK update of the transformed energy DF */
-    for (int a = 0; a < 9; ++a) hout[a] = hb[a] - d.wh * (hb[a] - heq[a]) + (1.0 - 0.5 * d.wh) * K[a];
+    for (int a = 0; a < 9; ++a)
+      hout[a] = hb[a] - d.wh * (hb[a] - heq[a]) + (1.0 - 0.5 * d.wh) * (K[a] + F[a]);
     return;
   }
   /* Two-rate update: the same transformed scheme written moment by moment.  The
@@ -443,8 +470,8 @@ void orc_collide_node(const orc_params *p, const double fb[9], const double hb[9
   const double ko = 0.0, so = 0.5;                     /* other moments, rate 1 */
   double mp[9];
   mp[I00] = 0.0;
-  mp[I10] = kf * mn[I10] + sf * mk[I10];
-  mp[I01] = kf * mn[I01] + sf * mk[I01];
+  mp[I10] = kf * mn[I10] + sf * (mk[I10] + (F[1] - F[3]));
+  mp[I01] = kf * mn[I01] + sf * (mk[I01] + (F[2] - F[4]));
   for (int i = IE; i <= I22; ++i) mp[i] = ko * mn[i] + so * mk[i];
   orc_pops_from_moments(1.0, mp, post);
   for (int a = 0; a < 9; ++a) hout[a] = heq[a] + post[a];
@@ -497,7 +524,15 @@ static void wall_prestep(const orc_params *p, double *f, double *h) {
       double fw[9], ff[9], hw[9], hf[9];
       orc_feq(rw, p->wall_ux[side], p->wall_uy[side], p->R * Tw, fw);
       orc_feq(r, vx, vy, p->R * t, ff);
-      for (int a = 0; a < 9; ++a) f[a * n + ib] = fw[a] + (fb[a] - ff[a]);
+      /* the stored DF is the transformed one, fbar = f - S/2 - C/2, so its
+       * equilibrium part is f^eq - S/2 at either node (C has no mass or
+       * momentum; its share stays in the extrapolated non-equilibrium part) */
+      double smw[9], smf[9], Sw[9], Sf[9];
+      orc_source_moments(node_ax(p, ib), node_ay(p, ib), p->wall_ux[side], p->wall_uy[side], smw);
+      orc_pops_from_moments(rw, smw, Sw);
+      orc_source_moments(node_ax(p, i_f), node_ay(p, i_f), vx, vy, smf);
+      orc_pops_from_moments(r, smf, Sf);
+      for (int a = 0; a < 9; ++a) f[a * n + ib] = (fw[a] - 0.5 * Sw[a]) + (fb[a] - (ff[a] - 0.5 * Sf[a]));
       if (p->thermal) {
         orc_heq_mode(rw, p->wall_ux[side], p->wall_uy[side], p->R * Tw, d.b, p->heq_moments, hw);
         orc_heq_mode(r, vx, vy, p->R * t, d.b, p->heq_moments, hf);
@@ -525,7 +560,7 @@ int orc_check_params(const orc_params *p) {
   if (!(p->tau_f > 0.5) || !(p->gamma > 1.0) || !(p->Pr > 0.0) || !(p->R > 0.0) || !(p->T0 > 0.0)) return 1;
   for (int s = 0; s < 4; ++s)
     if (p->bc[s] < 0 || p->bc[s] > 2) return 1;
-  if (p->wall_rho < 0 || p->wall_rho > 2 || p->heq_moments < 0 || p->heq_moments > 1 || p->h_collision < 0 || p->h_collision > 1) return 1;
+  if (p->wall_rho < 0 || p->wall_rho > 2 || p->heq_moments < 0 || p->heq_moments > 1 || p->h_collision < 0 || p->h_collision > 1 || p->h_force < 0 || p->h_force > 1) return 1;
   if ((p->bc[ORC_XLO] == ORC_PERIODIC) != (p->bc[ORC_XHI] == ORC_PERIODIC)) return 1;
   if ((p->bc[ORC_YLO] == ORC_PERIODIC) != (p->bc[ORC_YHI] == ORC_PERIODIC)) return 1;
   if (p->bc[ORC_XLO] == ORC_WALL || p->bc[ORC_XHI] == ORC_WALL) return 1; /* walls on y sides only */

@@ -32,6 +32,7 @@ struct tclbm_ctx {
   double *fields;        // library-owned, lazily allocated (4 * n doubles)
   int64_t steps;
   bool unstable;
+  uint64_t version;      // bumped whenever the launch template changes
   int strip_rows_req;
   int graph_chunk;
   hipGraphExec_t graph;  // replays graph_chunk steps starting from buffer 0
@@ -69,6 +70,7 @@ bool valid_params(const tclbm_params *p) {
   if (p->wall_rho < 0 || p->wall_rho > 2) return false;
   if (p->heq_moments < 0 || p->heq_moments > 1) return false;
   if (p->h_collision < 0 || p->h_collision > 1) return false;
+  if (p->h_force < 0 || p->h_force > 1) return false;
   if (p->accel_field != 0 && p->accel_field != 1) return false;
   for (int q = 0; q < 4; ++q) {
     if (p->bc[q] < kPeriodic || p->bc[q] > kWall) return false;
@@ -116,6 +118,7 @@ void fill_kparams(tclbm_ctx *c) {
   k.correction = p.correction;
   k.heq_mode = p.heq_moments;
   k.h_coll = p.h_collision;
+  k.h_force = p.h_force;
   k.wall_rho = p.wall_rho;
   k.R = p.R;
   k.T0 = p.T0;
@@ -298,6 +301,7 @@ void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p) {
   p->w2 = p->w3 = p->w4 = 1.0;
   p->thermal = 1;
   p->correction = 1;
+  p->h_force = 1;
   p->storage = TCLBM_STORE_F32;
   for (int q = 0; q < 4; ++q) {
     p->bc[q] = TCLBM_BC_PERIODIC;
@@ -430,6 +434,7 @@ tclbm_status tclbm_set_bc(tclbm_handle c, int32_t side, int32_t kind, double ux_
   c->k.wall_T[side] = (kind == kWall) ? T_w : c->p.T0;
   decompose(c);
   drop_graph(c);
+  ++c->version;
   return TCLBM_OK;
 }
 
@@ -439,6 +444,7 @@ tclbm_status tclbm_set_tuning(tclbm_handle c, int32_t strip_rows, int32_t graph_
   c->graph_chunk = graph_chunk;
   decompose(c);
   drop_graph(c);
+  ++c->version;
   return TCLBM_OK;
 }
 
@@ -587,6 +593,8 @@ tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_
 // ------------------------------------------------------------------ batches ---
 struct tclbm_batch {
   std::vector<tclbm_handle> m;  // members, in table order
+  std::vector<uint64_t> version;  // members' launch-template versions when tabled
+  std::vector<int64_t> steps;     // members' step counts the table's parity assumes
   int storage;
   hipStream_t stream;
   KParams *d_tab;    // device table (src/dst of the even steps)
@@ -596,8 +604,44 @@ struct tclbm_batch {
   hipGraphExec_t graph;
   bool graph_ok;
   int parity;        // 0: members' current state in the table's src
+  int strip_rows_req;  // batch strip height (0: automatic), overrides the members'
+  int strip_rows;      // the height in use
   char err[256];
 };
+
+// Strip height for a whole batch: enough waves over all members to fill the
+// chip a few times (each wave-row is a 62-column tile row), long strips
+// otherwise, since every strip re-pulls its halo rows.
+static int batch_auto_rows(const tclbm_batch *b) {
+  long long rowtiles = 0;
+  for (tclbm_handle h : b->m) rowtiles += (long long)h->k.ny * h->k.n_xtiles;
+  long long r = rowtiles / 32768;
+  return (int)(r < 1 ? 1 : (r > 32 ? 32 : r));
+}
+
+// Launch table and wave prefix sums for the current members, strip height,
+// and parity 0 = members' current buffers as src (device copies; synchronous).
+static hipError_t batch_upload(tclbm_batch *b) {
+  const int n = (int)b->m.size();
+  b->strip_rows = b->strip_rows_req > 0 ? b->strip_rows_req : batch_auto_rows(b);
+  std::vector<KParams> tab(n);
+  std::vector<int> start(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    tclbm_handle h = b->m[i];
+    tab[i] = h->k;
+    tab[i].src = h->buf[h->cur];
+    tab[i].dst = h->buf[1 - h->cur];
+    const int rows = b->strip_rows < h->k.ny ? b->strip_rows : h->k.ny;
+    tab[i].strip_rows = rows;
+    tab[i].n_strips = (h->k.ny + rows - 1) / rows;
+    start[i + 1] = start[i] + tab[i].n_xtiles * tab[i].n_strips;
+  }
+  b->total_waves = start[n];
+  b->parity = 0;
+  hipError_t e = hipMemcpy(b->d_tab, tab.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_start, start.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+  return e;
+}
 
 static void batch_drop_graph(tclbm_batch *b) {
   if (b->graph_ok) hipGraphExecDestroy(b->graph);
@@ -637,28 +681,22 @@ tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_ha
   // largest members first: their waves start first and the tail is short ones
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  auto work = [&](int i) { return (long long)b->m[i]->k.n_xtiles * b->m[i]->k.n_strips * b->m[i]->k.strip_rows; };
+  auto work = [&](int i) { return (long long)b->m[i]->k.n_xtiles * b->m[i]->k.ny; };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
   std::vector<tclbm_handle> sorted(n);
   for (int i = 0; i < n; ++i) sorted[i] = b->m[order[i]];
   b->m = sorted;
+  for (tclbm_handle h : b->m) {
+    b->version.push_back(h->version);
+    b->steps.push_back(h->steps);
+  }
   b->storage = members[0]->p.storage;
   b->stream = members[0]->stream;
   b->graph_chunk = 16;
-  std::vector<KParams> tab(n);
-  std::vector<int> start(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    tclbm_handle h = b->m[i];
-    tab[i] = h->k;
-    tab[i].src = h->buf[h->cur];
-    tab[i].dst = h->buf[1 - h->cur];
-    start[i + 1] = start[i] + h->k.n_xtiles * h->k.n_strips;
-  }
-  b->total_waves = start[n];
+  b->strip_rows_req = 0;
   hipError_t e = hipMalloc(&b->d_tab, sizeof(KParams) * n);
   if (e == hipSuccess) e = hipMalloc(&b->d_start, sizeof(int) * (n + 1));
-  if (e == hipSuccess) e = hipMemcpy(b->d_tab, tab.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(b->d_start, start.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = batch_upload(b);
   if (e != hipSuccess) {
     if (b->d_tab) hipFree(b->d_tab);
     if (b->d_start) hipFree(b->d_start);
@@ -671,8 +709,16 @@ tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_ha
 
 tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
   if (!b || nsteps < 0) return TCLBM_E_INVALID;
-  for (tclbm_handle h : b->m)
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    tclbm_handle h = b->m[i];
     if (h->unstable) return TCLBM_E_STATE;
+    // a member stepped alone or re-tuned since the table was built: the table's
+    // buffers or launch shape no longer describe it
+    if (h->version != b->version[i] || h->steps != b->steps[i]) {
+      snprintf(b->err, sizeof(b->err), "member %zu changed outside the batch", i);
+      return TCLBM_E_STATE;
+    }
+  }
   const int ch = b->stream ? b->graph_chunk : 0;
   int64_t n = nsteps;
   tclbm_status st = TCLBM_OK;
@@ -706,8 +752,10 @@ tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
   if (st == TCLBM_OK) st = batch_launch(b, n);
   // members' bookkeeping: the state now lives in the buffer the parity names
   const int64_t done = nsteps - (st == TCLBM_OK ? 0 : n);
-  for (tclbm_handle h : b->m) {
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    tclbm_handle h = b->m[i];
     h->steps += done;
+    b->steps[i] = h->steps;
     if (done & 1) h->cur = 1 - h->cur;
   }
   return st;
@@ -744,6 +792,19 @@ tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk) {
   batch_drop_graph(b);
   return TCLBM_OK;
 }
+
+tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows) {
+  if (!b || rows < 0) return TCLBM_E_INVALID;
+  // the table is rebuilt from the members' bookkeeping (current buffers),
+  // which restarts the parity at 0
+  (void)hipStreamSynchronize(b->stream);
+  b->strip_rows_req = rows;
+  batch_drop_graph(b);
+  if (batch_upload(b) != hipSuccess) return TCLBM_E_DEVICE;
+  return TCLBM_OK;
+}
+
+int32_t tclbm_batch_strip_rows(tclbm_batch_handle b) { return b ? b->strip_rows : -1; }
 
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b) {
   if (!b) return TCLBM_E_INVALID;

@@ -20,7 +20,7 @@ struct KParams {
   int nx, ny;
   int pitch;        // elements per stored row (>= nx)
   long long plane;  // elements per population plane (pitch * ny)
-  int thermal, correction, heq_mode, h_coll, wall_rho;
+  int thermal, correction, heq_mode, h_coll, h_force, wall_rho;
   int bc[4];
   double wall_ux[4], wall_uy[4], wall_T[4];
   double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;

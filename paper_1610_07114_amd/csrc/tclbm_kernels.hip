@@ -48,10 +48,19 @@ struct Store<kF64> {
   static __device__ __forceinline__ void st(T *p, long long i, double v) { p[i] = v; }
 };
 template <>
-struct Store<kF16> {  // IEEE half, round to nearest even
+struct Store<kF16> {
+  // IEEE half of the deviation times 2^10, round to nearest even.  The power
+  // of two scales exactly; it moves half's normal range (6.1e-5 .. 65504) to
+  // deviations 6.0e-8 .. 64, so the tiny perturbations from which an
+  // instability grows keep 11 significant bits instead of falling into
+  // subnormals.  |deviation| >= 64 overflows to inf (reported as unstable).
   using T = unsigned short;
-  static __device__ __forceinline__ float ld(const T *p, long long i) { return __half2float(__ushort_as_half(p[i])); }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = __half_as_ushort(__float2half_rn(v)); }
+  static __device__ __forceinline__ float ld(const T *p, long long i) {
+    return __half2float(__ushort_as_half(p[i])) * 0x1p-10f;
+  }
+  static __device__ __forceinline__ void st(T *p, long long i, float v) {
+    p[i] = __half_as_ushort(__float2half_rn(v * 0x1p10f));
+  }
 };
 template <>
 struct Store<kBF16> {  // bfloat16, round to nearest even
@@ -92,6 +101,7 @@ __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   c.correction = k.correction;
   c.heq_mode = k.heq_mode;
   c.h_coll = k.h_coll;
+  c.h_force = k.h_force;
   return c;
 }
 
@@ -154,76 +164,114 @@ __device__ __forceinline__ RowRef<R> row_ref(const KParams &k, const Consts<R> &
 // Pull the populations that arrive at (col.xc, y): f_a = P_a(x - e_a).  Links
 // from outside a non-periodic side bounce back halfway at rest:
 // f_a = P_opp(a)(x) (for WALL rows those values are never used).
-template <int S>
-__device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
-                                     typename Real<S>::T *f, typename Real<S>::T *h) {
-  using R = typename Real<S>::T;
-  using ST = typename Store<S>::T;
-  const ST *src = reinterpret_cast<const ST *>(k.src);
-  const R *shF = reinterpret_cast<const R *>(k.shiftF) + 9 * y;
-  const R *shH = reinterpret_cast<const R *>(k.shiftH) + 9 * y;
-  int ym, yp;
+// Row geometry of a pull: source rows of the three e_y classes and whether
+// links come from outside a non-periodic y side.
+struct RowSrc {
+  unsigned rm, rc, rp;  // element offsets of rows y-1 (e_y = +1 links), y, y+1
   bool outB, outT;
+};
+
+__device__ __forceinline__ RowSrc row_src(const KParams &k, int y) {
+  RowSrc r;
+  int ym, yp;
   if (k.bc[kYlo] == kPeriodic) {
     ym = (y == 0) ? k.ny - 1 : y - 1;
     yp = (y == k.ny - 1) ? 0 : y + 1;
-    outB = outT = false;
+    r.outB = r.outT = false;
   } else {
-    outB = (y == 0);
-    outT = (y == k.ny - 1);
-    ym = outB ? y : y - 1;
-    yp = outT ? y : y + 1;
+    r.outB = (y == 0);
+    r.outT = (y == k.ny - 1);
+    ym = r.outB ? y : y - 1;
+    yp = r.outT ? y : y + 1;
   }
-  // element offsets inside a plane (< 2^31): rows are wave-uniform, columns per lane
-  const unsigned rm = (unsigned)ym * k.pitch, rc = (unsigned)y * k.pitch, rp = (unsigned)yp * k.pitch;
+  r.rm = (unsigned)ym * k.pitch;
+  r.rc = (unsigned)y * k.pitch;
+  r.rp = (unsigned)yp * k.pitch;
+  return r;
+}
+
+// Phase 1 of a pull: issue the loads of the populations that arrive at
+// (col.xc, y), f_a = P_a(x - e_a), as stored (deviations of the source row).
+// Links from outside a non-periodic side bounce back halfway at rest,
+// f_a = P_opp(a)(x).  Interior tiles and rows take a select-free path.
+template <int S>
+__device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &col,
+                                           typename Real<S>::T *f, typename Real<S>::T *h) {
+  using ST = typename Store<S>::T;
+  const ST *src = reinterpret_cast<const ST *>(k.src);
+  const RowSrc rs = row_src(k, y);
   const long long hoff = 9 * k.plane;
-  if (k.bc[kXlo] == kPeriodic && !outB && !outT) {
-    // fast path: every link comes from inside the lattice
+  if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      const unsigned off = (kEy[a] > 0 ? rm : (kEy[a] < 0 ? rp : rc)) +
+      const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
                            (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
       const ST *base = src + a * k.plane;
       f[a] = Store<S>::ld(base, off);
-      if (kEy[a] != 0) f[a] += shF[a];
-      if (k.thermal) {
-        h[a] = Store<S>::ld(base + hoff, off);
-        if (kEy[a] != 0) h[a] += shH[a];
-      }
+      if (k.thermal) h[a] = Store<S>::ld(base + hoff, off);
     }
     return;
   }
-  // edge tiles and rows: links from outside a non-periodic side bounce back
-  // halfway at rest, f_a = P_opp(a)(x) (rest state symmetric: no shift)
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
     const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
-    const unsigned sr = kEy[a] > 0 ? rm : (kEy[a] < 0 ? rp : rc);
-    const bool oy = kEy[a] > 0 ? outB : (kEy[a] < 0 ? outT : false);
+    const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
+    const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
     const bool bb = ox || oy;
     const ST *base = src + (bb ? kOpp[a] : a) * k.plane;
-    const unsigned off = bb ? rc + (unsigned)col.xc : sr + (unsigned)sx;
+    const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
     f[a] = Store<S>::ld(base, off);
-    if (kEy[a] != 0 && !bb) f[a] += shF[a];
-    if (k.thermal) {
-      h[a] = Store<S>::ld(base + hoff, off);
-      if (kEy[a] != 0 && !bb) h[a] += shH[a];
+    if (k.thermal) h[a] = Store<S>::ld(base + hoff, off);
+  }
+}
+
+// Phase 2: re-express the pulled deviations against this row's reference,
+// adding r_a(source row) - r_a(y) (bounced links stay in the row: the rest
+// state is symmetric, no shift).
+template <int S>
+__device__ __forceinline__ void pull_shift(const KParams &k, int y, const Col &col,
+                                           typename Real<S>::T *f, typename Real<S>::T *h) {
+  using R = typename Real<S>::T;
+  const R *shF = reinterpret_cast<const R *>(k.shiftF) + 9 * y;
+  const R *shH = reinterpret_cast<const R *>(k.shiftH) + 9 * y;
+  const RowSrc rs = row_src(k, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    if (kEy[a] == 0) continue;
+    const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
+    const bool oy = kEy[a] > 0 ? rs.outB : rs.outT;
+    const bool bb = ox || oy;
+    if (!bb) {
+      f[a] += shF[a];
+      if (k.thermal) h[a] += shH[a];
     }
   }
+}
+
+template <int S>
+__device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
+                                     typename Real<S>::T *f, typename Real<S>::T *h) {
+  pull_issue<S>(k, y, col, f, h);
+  pull_shift<S>(k, y, col, f, h);
 }
 
 // Populations of a WALL row node by non-equilibrium extrapolation from the
 // adjacent fluid node (I):
 // X(x_b) = X^eq(rho_w, u_w, T_w) + [X(x_f) - X^eq(rho_f, u_f, T_f)],
-// in deviations: d_w = (f^eq_w - r_w) - (f^eq_I - r_I) + d_I.
+// in deviations: d_w = (f^eq_w - r_w) - (f^eq_I - r_I) + d_I.  The stored f is
+// the transformed fbar = f - S/2 - C/2, whose equilibrium part is f^eq - S/2
+// (at each node's own rho, u and a); C, without mass or momentum, stays in the
+// extrapolated non-equilibrium part.
 // On entry dw holds the deviations pulled at the wall node; those that came
 // from the fluid and the tangential ones fix rho_w (default reading): with the
 // rest reference, k0 + 2 k_in = rho_r + the same combination of deviations.
 template <class R>
 __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const RowRef<R> &qw,
                                           const RowRef<R> &qI, const R *dI, const R *gI, const Macro<R> &mI,
-                                          R aI_n, R aW_n, R *dw, R *gw) {
+                                          R axI, R ayI, R axW, R ayW, R *dw, R *gw) {
+  const R aI_n = (side == kYlo) ? -ayI : ayI;
+  const R aW_n = (side == kYlo) ? -ayW : ayW;
   const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
   const R thw = k.thermal ? c.R_ * (R)k.wall_T[side] : c.R_ * c.T0;
   R drw;
@@ -240,11 +288,13 @@ __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, 
     drw = (D - qw.rho * (un - R(0.5) * aW_n)) / den;
   }
   const R dthw = thw - qw.th;
-  R ew[9], ef[9];
+  R ew[9], ef[9], sw[9], sf[9];
   feq_dev(qw, drw, uwx, uwy, dthw, ew);
   feq_dev(qI, mI.drho, mI.ux, mI.uy, mI.dth, ef);
+  source9(qw.rho + drw, uwx, uwy, axW, ayW, sw);
+  source9(mI.rho, mI.ux, mI.uy, axI, ayI, sf);
 #pragma unroll
-  for (int a = 0; a < 9; ++a) dw[a] = ew[a] - ef[a] + dI[a];
+  for (int a = 0; a < 9; ++a) dw[a] = (ew[a] - ef[a]) - R(0.5) * (sw[a] - sf[a]) + dI[a];
   if (k.thermal) {
     const R Ew = R(0.5) * (c.b * thw + uwx * uwx + uwy * uwy);
     const R sgw = drw * Ew + qw.rho * (R(0.5) * c.b * dthw + R(0.5) * (uwx * uwx + uwy * uwy));
@@ -286,6 +336,21 @@ __device__ __forceinline__ void get_row(const KParams &k, const Consts<typename 
   finish(k, c, y, col.xc, s);
 }
 
+// State of row y (not a WALL row) from loads issued earlier by pull_issue.
+template <int S>
+__device__ __forceinline__ void get_row_raw(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
+                                            const Col &col, const typename Real<S>::T *rf,
+                                            const typename Real<S>::T *rh, RowState<typename Real<S>::T> &s) {
+  s.q = row_ref(k, c, y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    s.f[a] = rf[a];
+    if (k.thermal) s.h[a] = rh[a];
+  }
+  pull_shift<S>(k, y, col, s.f, s.h);
+  finish(k, c, y, col.xc, s);
+}
+
 // State of the WALL row y whose fluid neighbour state is `in`.
 template <int S>
 __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
@@ -299,9 +364,7 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   R axI, ayI, axW, ayW;
   node_accel<R>(k, yf, col.xc, axI, ayI);
   node_accel<R>(k, y, col.xc, axW, ayW);
-  const R aI_n = (side == kYlo) ? -ayI : ayI;
-  const R aW_n = (side == kYlo) ? -ayW : ayW;
-  wall_node<R>(k, c, side, s.q, in.q, in.f, in.h, in.m, aI_n, aW_n, s.f, s.h);
+  wall_node<R>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, s.f, s.h);
   finish(k, c, y, col.xc, s);
 }
 
@@ -354,6 +417,19 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 // ------------------------------------------------------------ step kernel ---
 constexpr int kStepWaves = 4;
 
+// Build-time launch shape of the step kernels (defaults chosen by measurement).
+#ifndef TCLBM_PREFETCH
+#define TCLBM_PREFETCH 0
+#endif
+#ifndef TCLBM_WAVES_PER_EU
+#define TCLBM_WAVES_PER_EU 0
+#endif
+#if TCLBM_WAVES_PER_EU > 0
+#define TCLBM_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_WAVES_PER_EU, TCLBM_WAVES_PER_EU)))
+#else
+#define TCLBM_OCC
+#endif
+
 // The march of one wave over its (x tile, strip) of lattice k.
 template <int S>
 __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
@@ -372,6 +448,26 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
   RowState<R> cur, nxt;
   R qy_m1 = R(0), qy_m2 = R(0);
   int j;
+  if (r1 - r0 == 1 && (yper || (r0 >= 3 && r0 <= ny - 4))) {
+    // single-row strip away from the edges (small lattices): the three rows it
+    // needs are independent, so all their loads are issued before any is used
+    const int ya = (r0 == 0) ? ny - 1 : r0 - 1, yb = (r0 == ny - 1) ? 0 : r0 + 1;
+    RowState<R> lo, hi;
+    pull_issue<S>(k, ya, col, lo.f, lo.h);
+    pull_issue<S>(k, r0, col, cur.f, cur.h);
+    pull_issue<S>(k, yb, col, hi.f, hi.h);
+    lo.q = row_ref(k, c, ya);
+    pull_shift<S>(k, ya, col, lo.f, lo.h);
+    finish(k, c, ya, col.xc, lo);
+    hi.q = row_ref(k, c, yb);
+    pull_shift<S>(k, yb, col, hi.f, hi.h);
+    finish(k, c, yb, col.xc, hi);
+    cur.q = row_ref(k, c, r0);
+    pull_shift<S>(k, r0, col, cur.f, cur.h);
+    finish(k, c, r0, col.xc, cur);
+    collide_store<S>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl);
+    return;
+  }
   if (!yper && r0 == 0) {
     // bottom edge: row 0 needs u(1-theta) of rows 1 and 2 (one-sided difference)
     get_row<S>(k, c, 1, col, nxt);                       // row 1 (ny >= 3: a fluid row)
@@ -407,6 +503,11 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
     j = r0;
   }
 
+  // Optional software pipeline: the loads of the row after next are issued
+  // before the current row's collision (costs 18 registers per lane).
+  R raw_f[9], raw_h[9];
+  bool have_raw = false;
+  constexpr bool kPrefetch = TCLBM_PREFETCH != 0;
   for (; j < r1; ++j) {
     if (!yper && j == ny - 1) {  // top edge: one-sided difference with the rows below
       const R Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_m1 + qy_m2);
@@ -414,8 +515,19 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
       break;
     }
     const int yn = (j == ny - 1) ? 0 : j + 1;
-    if (!yper && is_wall_row(k, yn)) get_wall_row<S>(k, c, yn, col, cur, nxt);
+    if (have_raw) get_row_raw<S>(k, c, yn, col, raw_f, raw_h, nxt);
+    else if (!yper && is_wall_row(k, yn)) get_wall_row<S>(k, c, yn, col, cur, nxt);
     else get_row<S>(k, c, yn, col, nxt);
+    // prefetch the row the next iteration needs, unless it is the top edge
+    // (no row above) or a WALL row (derived, not pulled)
+    have_raw = false;
+    if (kPrefetch && j + 1 < r1 && (yper || yn != ny - 1)) {
+      const int ynn = (yn == ny - 1) ? 0 : yn + 1;
+      if (yper || !is_wall_row(k, ynn)) {
+        pull_issue<S>(k, ynn, col, raw_f, raw_h);
+        have_raw = true;
+      }
+    }
     const R Dy = R(0.5) * (nxt.qy - qy_m1);
     collide_store<S>(k, c, j, col, store, cur, Dy, xl);
     qy_m2 = qy_m1;
@@ -425,7 +537,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
 }
 
 template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void step_kernel(KParams k) {
   const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
   if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
   march<S>(k, wave, threadIdx.x & 63);
@@ -436,7 +548,7 @@ __global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
 // n_xtiles * n_strips, wave_start[n] = total); waves of one instance are
 // contiguous, ordered as the table (the autotuner orders the table).
 template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel(const KParams *__restrict__ tab,
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void batch_step_kernel(const KParams *__restrict__ tab,
                                                                      const int *__restrict__ wave_start,
                                                                      int n_inst, int parity) {
   const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
@@ -707,16 +819,24 @@ hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipSt
 // achievable HBM bandwidth and to calibrate byte counters.
 __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                    long long n16) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // four independent 16-byte loads in flight per thread
   const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
   const long long n16 = (long long)(bytes / 16);
   if (n16 <= 0) return hipSuccess;
-  long long blocks = (n16 + 255) / 256;
-  if (blocks > 256 * 64) blocks = 256 * 64;
+  long long blocks = (n16 + 4 * 256 - 1) / (4 * 256);
+  if (blocks > 256 * 32) blocks = 256 * 32;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src),
                      reinterpret_cast<uint4 *>(dst), n16);
   return hipGetLastError();

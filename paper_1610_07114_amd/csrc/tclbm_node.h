@@ -125,7 +125,7 @@ TC_HD void ref_central(const RowRef<R> &q, R ux, R uy, R k[3][3]) {
 template <class R>
 struct Consts {
   R R_, T0, b, w1, w2, w3, w4, wh, inv_tau_hf;
-  int thermal, correction, heq_mode, h_coll;
+  int thermal, correction, heq_mode, h_coll, h_force;
   R two_b, inv_RT0;  // 2/b and 1/(R T0)
 };
 
@@ -311,11 +311,27 @@ TC_HD void collide(const Consts<R> &c, const RowRef<R> &q, const R *d, const R *
 #pragma unroll
   for (int a = 0; a < 9; ++a) K[a] *= c.inv_tau_hf;
 
+  // Body-force source of the energy DF: the force changes the equilibrium
+  // energy flux (rho E + p) u by (rho E + p) a per step, which the printed
+  // scheme leaves to the Chapman-Enskog flux as a spurious -(1/w_h - 1/2)
+  // (rho E + p) a.  Populations: half of each component on the two axis
+  // links, entering with the (1 - w_h/2) factor of the transformed scheme.
+  const R kk = R(1) - R(0.5) * c.wh;
+  R Fx = R(0), Fy = R(0);
+  if (c.h_force) {
+    const R hf = R(0.5) * kk * rho * ((R(0.5) * c.b + R(1)) * th + hu2);  // th = R T
+    Fx = hf * ax;
+    Fy = hf * ay;
+  }
+
   if (c.h_coll == 1) {
     // BGK update of the transformed energy DF (Section 4)
-    const R kk = R(1) - R(0.5) * c.wh;
 #pragma unroll
     for (int a = 0; a < 9; ++a) Q[a] = g[a] - c.wh * (g[a] - he[a]) + kk * K[a];
+    Q[1] += Fx;
+    Q[3] -= Fx;
+    Q[2] += Fy;
+    Q[4] -= Fy;
     return;
   }
   // Two-rate update: energy-flux moments relax with w_h, all others with 1.
@@ -329,10 +345,10 @@ TC_HD void collide(const Consts<R> &c, const RowRef<R> &q, const R *d, const R *
   const R gg = R(0.5) * (R(1) - c.wh);
 #pragma unroll
   for (int a = 0; a < 9; ++a) Q[a] = he[a] + R(0.5) * K[a];
-  Q[1] += gg * Gx;
-  Q[3] -= gg * Gx;
-  Q[2] += gg * Gy;
-  Q[4] -= gg * Gy;
+  Q[1] += gg * Gx + Fx;
+  Q[3] -= gg * Gx + Fx;
+  Q[2] += gg * Gy + Fy;
+  Q[4] -= gg * Gy + Fy;
 }
 
 // Force source S (Section 3) as populations: its only non-zero central moments

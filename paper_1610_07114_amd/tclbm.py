@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libtclbm.so")
+# TCLBM_LIB may name another build of the same library (A/B of kernel variants)
+LIB_PATH = os.environ.get("TCLBM_LIB") or os.path.join(_HERE, "_lib", "libtclbm.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSTABLE = range(6)
 STORE = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
@@ -32,7 +33,7 @@ class tclbm_params(ctypes.Structure):
         ("ax", ctypes.c_double), ("ay", ctypes.c_double),
         ("thermal", ctypes.c_int32), ("correction", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("wall_rho", ctypes.c_int32), ("heq_moments", ctypes.c_int32), ("h_collision", ctypes.c_int32),
-        ("accel_field", ctypes.c_int32),
+        ("h_force", ctypes.c_int32), ("accel_field", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 4),
         ("wall_ux", ctypes.c_double * 4), ("wall_uy", ctypes.c_double * 4), ("wall_T", ctypes.c_double * 4),
     ]
@@ -53,7 +54,8 @@ EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_s
            "tclbm_step_timed", "tclbm_moments", "tclbm_steps_done", "tclbm_read_state", "tclbm_set_tuning",
            "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
            "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
-           "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_destroy"]
+           "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_set_strip_rows",
+           "tclbm_batch_strip_rows", "tclbm_batch_destroy"]
 
 
 def _load():
@@ -108,6 +110,10 @@ def _load():
     lib.tclbm_batch_waves.restype = ctypes.c_int64
     lib.tclbm_batch_set_graph_chunk.argtypes = [H, ctypes.c_int32]
     lib.tclbm_batch_set_graph_chunk.restype = ctypes.c_int
+    lib.tclbm_batch_set_strip_rows.argtypes = [H, ctypes.c_int32]
+    lib.tclbm_batch_set_strip_rows.restype = ctypes.c_int
+    lib.tclbm_batch_strip_rows.argtypes = [H]
+    lib.tclbm_batch_strip_rows.restype = ctypes.c_int32
     lib.tclbm_batch_destroy.argtypes = [H]
     lib.tclbm_batch_destroy.restype = ctypes.c_int
     return lib
@@ -231,6 +237,14 @@ def tclbm_batch_set_graph_chunk(b, chunk: int):
     _chk(_lib.tclbm_batch_set_graph_chunk(b, int(chunk)))
 
 
+def tclbm_batch_set_strip_rows(b, rows: int):
+    _chk(_lib.tclbm_batch_set_strip_rows(b, int(rows)))
+
+
+def tclbm_batch_strip_rows(b) -> int:
+    return int(_lib.tclbm_batch_strip_rows(b))
+
+
 def tclbm_batch_destroy(b):
     _chk(_lib.tclbm_batch_destroy(b))
 
@@ -260,10 +274,13 @@ class Lattice:
         if self.nbytes == 0:
             raise TclbmError(E_INVALID, "invalid parameters")
         self.device = torch.device(device)
-        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         # a stream of its own (default priority): the legacy default stream
-        # cannot be captured into HIP graphs
+        # cannot be captured into HIP graphs.  The buffer is allocated with that
+        # stream current, so torch's caching allocator does not hand its memory
+        # to work on another stream while the library's kernels may still use it.
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        with torch.cuda.stream(self.stream):
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         self.h = tclbm_create(p, self.buf.data_ptr(), self.nbytes, self.stream.cuda_stream, case.rho, case.ux,
                               case.uy, case.T if case.T is not None else case.rho, case.ax_field, case.ay_field)
 
@@ -322,6 +339,13 @@ class Batch:
 
     def set_graph_chunk(self, chunk: int):
         tclbm_batch_set_graph_chunk(self.h, chunk)
+
+    def set_strip_rows(self, rows: int):
+        tclbm_batch_set_strip_rows(self.h, rows)
+
+    @property
+    def strip_rows(self) -> int:
+        return tclbm_batch_strip_rows(self.h)
 
     def close(self):
         if self.h is not None:

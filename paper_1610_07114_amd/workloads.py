@@ -157,12 +157,6 @@ def rayleigh_benard(nx: int = 512, ny: int = 256, Ra: float = 1e5, Pr: float = 0
         meta=dict(Ra=Ra, H=H, dT=dT, kappa=P["kappa"], nu=P["nu"], g=P["g"], uc=uc, seed=seed))
 
 
-def nusselt(case: Case, uy: np.ndarray, T: np.ndarray) -> float:
-    """Nu = 1 + <u_y (T - T0)> H / (kappa dT), <.> over all nodes, kappa = nu/Pr."""
-    m = case.meta
-    return 1.0 + float(np.mean(uy * (T - case.T0))) * m["H"] / (m["kappa"] * m["dT"])
-
-
 # --------------------------------------------------------------------------------
 def shock_tube(nx: int = 8192, ny: int = 4, rho_left: float = 1.5, rho_right: float = 1.0, T: float = 1.0,
                w1: float = 1.887, gamma: float = 1.4, Pr: float = 0.71, steps: int = 4000) -> Case:

@@ -1,0 +1,120 @@
+#!/usr/bin/env python3
+"""Writes the stored FP64 Nusselt-number histories that the GPU Nusselt tests
+compare against.  Calls only the oracle and the seeded input generators.
+
+  python tests/golden/make_nu_golden.py batch   # seeded subset of the batched RB workload
+  python tests/golden/make_nu_golden.py rb512   # 512x256 Rayleigh-Benard, 2e5 steps
+
+Nu follows the Section 5D definition (oracle.nusselt).  A run lasts 50 H/u_c
+(the batched subset) or 2e5 steps (512x256); Nu is sampled on a fixed step
+schedule stored with the values, and the reference value is its mean over the
+last 10 H/u_c.  Each history also records how steady it is: the largest
+relative deviation of the samples in that window from their mean.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))
+
+import numpy as np  # noqa: E402
+
+import oracle as O  # noqa: E402
+from paper_1610_07114_amd import workloads as W  # noqa: E402
+
+BATCH_SEED = 0
+BATCH_N = 256
+TAU_MIN = 0.55   # below this the default scheme is linearly unstable (two-rate energy update)
+
+
+def schedule(H: int, uc: float, total_tu: float = 50.0, window_tu: float = 10.0):
+    tu = H / uc
+    every = max(1, int(round(tu / 4)))
+    total = int(round(total_tu * tu / every)) * every
+    avg_from = total - int(round(window_tu * tu / every)) * every
+    return every, total, avg_from
+
+
+def run_history(args):
+    case, every, total, avg_from, threads = args
+    from helpers import oracle_lattice
+    O.set_num_threads(threads)
+    L = oracle_lattice(case)
+    m = case.meta
+    steps, nus = [], []
+    t0 = time.perf_counter()
+    done = 0
+    while done < total:
+        L.step(every)
+        done += every
+        _, _, uy, T = L.macros()
+        nu = O.nusselt(uy, T, case.T0, m["H"], m["kappa"], m["dT"])
+        if not math.isfinite(nu):
+            break
+        steps.append(done)
+        nus.append(nu)
+    win = [n for s, n in zip(steps, nus) if s > avg_from]
+    mean = float(np.mean(win)) if win and len(steps) * every == total else float("nan")
+    dev = float(np.max(np.abs(np.array(win) - mean)) / abs(mean)) if win and math.isfinite(mean) else float("nan")
+    return dict(steps=steps, nu=nus, nu_mean=mean, unsteadiness=dev, seconds=round(time.perf_counter() - t0, 1))
+
+
+def batch_subset(count: int = 12, nmax: int = 64):
+    specs = W.batched_rb_specs(BATCH_N, seed=BATCH_SEED)
+    picked = []
+    for i, s in enumerate(specs):
+        c = W.rb_from_spec(s)
+        if s["ny"] <= nmax and c.tau_f >= TAU_MIN:
+            picked.append((i, s, c))
+        if len(picked) == count:
+            break
+    return picked
+
+
+def main():
+    which = sys.argv[1] if len(sys.argv) > 1 else "batch"
+    O.build()
+    if which == "batch":
+        picked = batch_subset()
+        jobs = []
+        for i, s, c in picked:
+            every, total, avg_from = schedule(c.meta["H"], c.meta["uc"])
+            jobs.append((c, every, total, avg_from, 1))
+        with ProcessPoolExecutor(max_workers=int(os.environ.get("NU_WORKERS", "6"))) as ex:
+            hist = list(ex.map(run_history, jobs))
+        out = dict(workload=f"batched Rayleigh-Benard specs (n={BATCH_N}, seed={BATCH_SEED}), instances with "
+                            f"N <= 64 and tau_f >= {TAU_MIN}, first {len(picked)}",
+                   instances=[])
+        for (i, s, c), (_, every, total, avg_from, _), h in zip(picked, jobs, hist):
+            out["instances"].append(dict(index=i, spec=s, tau_f=c.tau_f, every=every, total=total,
+                                         avg_from=avg_from, **h))
+            print(f"instance {i} {s['nx']}x{s['ny']} Ra {s['Ra']:.4g} Pr {s['Pr']:.3f} tau {c.tau_f:.4f}: "
+                  f"Nu {h['nu_mean']:.6f} unsteadiness {h['unsteadiness']:.2e} ({h['seconds']} s)", flush=True)
+        path = os.path.join(HERE, "rb_batch_nu_fp64.json")
+    elif which == "rb512":
+        c = W.rayleigh_benard(nx=512, ny=256, Ra=1e5, Pr=0.71, seed=0)
+        every, total = 1000, 200000
+        avg_from = total - int(round(10 * c.meta["H"] / c.meta["uc"] / every)) * every
+        h = run_history((c, every, total, avg_from, int(os.environ.get("NU_THREADS", "6"))))
+        out = dict(workload="rayleigh_benard 512x256, Ra 1e5, Pr 0.71, seed 0", every=every, total=total,
+                   avg_from=avg_from, **h)
+        print(f"512x256: Nu(end) {h['nu'][-1]:.6f} mean {h['nu_mean']:.6f} unsteadiness {h['unsteadiness']:.2e} "
+              f"({h['seconds']} s)", flush=True)
+        path = os.path.join(HERE, "rb512x256_nu_fp64.json")
+    else:
+        raise SystemExit(f"unknown set {which}")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

@@ -235,7 +235,12 @@ def test_batch_equals_members_alone_bitwise(T):
     lats = [T.Lattice(cs, storage="f32", stream=stream) for cs in cases]
     b = T.Batch(lats)
     b.set_graph_chunk(16)
-    b.step(75)
+    b.step(33)
+    b.set_strip_rows(5)          # the batch's own launch shape, changed mid-run
+    assert b.strip_rows == 5
+    b.step(37)
+    b.set_strip_rows(0)
+    b.step(5)
     b.close()
     for lat, ref in zip(lats, alone):
         assert lat.steps == 75

@@ -1,0 +1,172 @@
+"""GPU tests of the batched workload and the serving loop: results in the mix
+equal results alone (bitwise: every lattice's arithmetic is independent of the
+batch it runs in), admission by footprint queues requests that do not fit, and
+Nusselt numbers from the device FP64 reductions agree with stored FP64 oracle
+histories (1e-3 relative for FP32 storage, 5e-3 for 16-bit storage)."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_07114_amd import tclbm
+    return tclbm
+
+
+def small_stream(S, n=10, seed=3):
+    reqs = S.make_requests(n, rate=1.0, seed=seed, nmin=32, nmax=90, time_units=0.25)
+    for r in reqs:
+        r.arrival = 0.0
+    return reqs
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_serving_mix_equals_alone(T, storage):
+    import torch
+    from paper_1610_07114_amd import serving as S
+    reqs = small_stream(S)
+    say(f"case serving stream of {len(reqs)} requests {storage}, 3 slots, vs alone: "
+        + ", ".join(f"{r.kind} {r.nx}x{r.ny} {r.steps}" for r in reqs))
+    srv = S.Server(storage=storage, max_slots=3, hbm_budget=1 << 34, keep_states=[r.rid for r in reqs])
+    res = srv.run(reqs, realtime=False)
+    assert [r.rid for r in res] == [r.rid for r in reqs]
+    # with 3 slots, later requests were admitted while earlier ones ran
+    assert any(r.admitted > 0 for r in res)
+    stream = torch.cuda.Stream()
+    for req, r in zip(reqs, res):
+        lat = T.Lattice(req.case(), storage=storage, stream=stream)
+        lat.step(req.steps)
+        ref = lat.read_state()
+        _, _, _, _, s = lat.moments(fields=False)
+        lat.close()
+        assert r.status == "ok"
+        assert np.array_equal(r.state, ref), f"request {req.rid} differs from its run alone"
+        if req.kind == "rb":
+            assert r.nu == S.nusselt_from_sums(req.case(), s)
+
+
+def test_admission_by_footprint(T):
+    """A budget of two large lattices' footprint: requests beyond it wait in the
+    queue and are admitted as memory frees; resident bytes never exceed it."""
+    from paper_1610_07114_amd import serving as S
+    reqs = small_stream(S, n=8, seed=5)
+    srv = S.Server(storage="f16", hbm_budget=1, max_slots=64, keep_states=[r.rid for r in reqs])
+    fp = [srv.footprint(r) for r in reqs]
+    srv.budget = 2 * max(fp)
+    say(f"case admission with budget {srv.budget} bytes, footprints {fp}")
+    res = srv.run(reqs, realtime=False)
+    # replay the admission decisions: at no time did resident bytes exceed the budget
+    events = sorted([(r.admitted, +f) for r, f in zip(res, fp)] + [(r.finished, -f) for r, f in zip(res, fp)],
+                    key=lambda e: (e[0], e[1]))
+    used, peak = 0, 0
+    for _, d in events:
+        used += d
+        peak = max(peak, used)
+    assert peak <= srv.budget
+    assert all(r.status == "ok" for r in res)
+
+
+def test_batch_rejects_member_stepped_alone(T):
+    import torch
+    from paper_1610_07114_amd import workloads as W
+    stream = torch.cuda.Stream()
+    a = T.Lattice(W.couette(), storage="f32", stream=stream)
+    b = T.Lattice(W.uniform_noise(40, 20, seed=1), storage="f32", stream=stream)
+    bt = T.Batch([a, b])
+    bt.step(3)
+    a.step(1)
+    with pytest.raises(T.TclbmError) as ei:
+        bt.step(2)
+    assert ei.value.status == T.E_STATE
+    bt.close()
+    a.close()
+    b.close()
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-3), ("f16", 5e-3), ("bf16", 5e-3)])
+def test_batched_nusselt_vs_fp64(T, storage, tol):
+    """The seeded steady subset of the batched RB workload, run as one batch for
+    50 H/u_c; Nu time-averaged over the last 10 H/u_c on the stored schedule."""
+    import torch
+    from paper_1610_07114_amd import serving as S
+    from paper_1610_07114_amd import workloads as W
+    g = _golden("rb_batch_nu_fp64.json")
+    insts = [i for i in g["instances"] if math.isfinite(i["nu_mean"]) and i["unsteadiness"] < 0.3]
+    assert len(insts) >= 8
+    say(f"case batched Nu {storage}: {len(insts)} instances " + ", ".join(
+        f"{i['spec']['nx']}x{i['spec']['ny']}" for i in insts))
+    stream = torch.cuda.Stream()
+    cases = [W.rb_from_spec(i["spec"]) for i in insts]
+    lats = [T.Lattice(c, storage=storage, stream=stream) for c in cases]
+    b = T.Batch(lats)
+    b.set_graph_chunk(16)
+    points = sorted({s for i in insts for s in range(i["every"], i["total"] + 1, i["every"])})
+    samples = [[] for _ in insts]
+    done = 0
+    for p in points:
+        b.step(p - done)
+        done = p
+        for k, (i, lat, c) in enumerate(zip(insts, lats, cases)):
+            if p % i["every"] == 0 and i["avg_from"] < p <= i["total"]:
+                _, _, _, _, s = lat.moments(fields=False)
+                samples[k].append(S.nusselt_from_sums(c, s))
+    b.close()
+    worst = 0.0
+    for i, smp, lat in zip(insts, samples, lats):
+        nu = float(np.mean(smp))
+        err = abs(nu - i["nu_mean"]) / abs(i["nu_mean"])
+        say(f"  instance {i['index']} {i['spec']['nx']}x{i['spec']['ny']}: Nu {nu:.6f} vs FP64 "
+            f"{i['nu_mean']:.6f}, rel err {err:.2e}")
+        worst = max(worst, err)
+        lat.close()
+    assert worst < tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-3), ("f16", 5e-3)])
+def test_rb512_nusselt_vs_fp64(T, storage, tol):
+    """512x256 Rayleigh-Benard, Ra 1e5, Pr 0.71, 2e5 steps: Nu every 1000 steps
+    against the stored FP64 oracle history (end value and window mean)."""
+    from paper_1610_07114_amd import serving as S
+    from paper_1610_07114_amd import workloads as W
+    g = _golden("rb512x256_nu_fp64.json")
+    case = W.rayleigh_benard(nx=512, ny=256, Ra=1e5, Pr=0.71, seed=0)
+    say(f"case rayleigh-benard 512x256 {storage} {g['total']} steps, Nu every {g['every']}")
+    lat = T.Lattice(case, storage=storage)
+    nus = []
+    for _ in range(g["total"] // g["every"]):
+        lat.step(g["every"])
+        _, _, _, _, s = lat.moments(fields=False)
+        nus.append(S.nusselt_from_sums(case, s))
+    lat.close()
+    steps = list(range(g["every"], g["total"] + 1, g["every"]))
+    win = [n for st, n in zip(steps, nus) if st > g["avg_from"]]
+    mean = float(np.mean(win))
+    e_end = abs(nus[-1] - g["nu"][-1]) / g["nu"][-1]
+    e_mean = abs(mean - g["nu_mean"]) / g["nu_mean"]
+    say(f"  Nu end {nus[-1]:.6f} vs {g['nu'][-1]:.6f} ({e_end:.2e}); mean {mean:.6f} vs {g['nu_mean']:.6f} "
+        f"({e_mean:.2e})")
+    assert e_mean < tol and e_end < tol

@@ -56,7 +56,7 @@ def test_state_bytes_plan(T):
 
 @pytest.mark.parametrize("field,value", [("nx", 2), ("ny", 0), ("tau_f", 0.5), ("gamma", 1.0), ("Pr", 0.0),
                                          ("w2", 2.0), ("w3", 0.0), ("storage", 7), ("R", 0.5),
-                                         ("wall_rho", 3), ("h_collision", 2), ("thermal", 2),
+                                         ("wall_rho", 3), ("h_collision", 2), ("h_force", 2), ("thermal", 2),
                                          ("bc", (2, 2, 0, 0)), ("bc", (1, 0, 0, 0)), ("bc", (0, 0, 2, 0))])
 def test_invalid_parameters_rejected(T, field, value):
     p = T.tclbm_default_params(16, 16)
@@ -128,13 +128,13 @@ def _node_case(seed):
     w2, w3, w4 = rng.uniform(0.3, 1.9, 3)
     g = float(rng.choice([1.4, 5 / 3, 1.3]))
     Pr = rng.uniform(0.5, 7)
-    hm, hc = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+    hm, hc, hfo = int(rng.integers(0, 2)), int(rng.integers(0, 2)), int(rng.integers(0, 2))
     th = 0 if seed % 7 == 3 else 1
     p = O.Params(nx=3, ny=3, tau_f=tau, w2=w2, w3=w3, w4=w4, gamma=g, Pr=Pr, heq_moments=hm, h_collision=hc,
-                 thermal=th)
+                 h_force=hfo, thermal=th)
     b, R, w1 = 2 / (g - 1), 1 / 3, 1 / tau
     wh = 1 / ((tau - 0.5) / Pr + 0.5)
-    cst = np.array([R, 1.0, b, w1, w2, w3, w4, wh, w1 * (Pr - 1), th, 1, hm, hc])
+    cst = np.array([R, 1.0, b, w1, w2, w3, w4, wh, w1 * (Pr - 1), th, 1, hm, hc, hfo])
     fb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4)
     hb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4) * 0.8
     # a row reference near, not at, the node state (athermal: theta_r = R T0)
