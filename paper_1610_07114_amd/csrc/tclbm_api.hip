@@ -57,6 +57,8 @@ bool valid_params(const tclbm_params *p) {
   if (!p) return false;
   if (p->nx < 3 || p->ny < 3) return false;
   if ((long long)p->nx * p->ny > (1LL << 28)) return false;
+  // kernels index within a population plane with 32-bit element offsets
+  if (up((size_t)p->nx, 64) * (size_t)p->ny >= (1ULL << 32)) return false;
   if (!(std::isfinite(p->R) && std::isfinite(p->T0) && p->R > 0 && p->T0 > 0)) return false;
   if (std::fabs(p->R * p->T0 - 1.0 / 3.0) > 1e-12) return false;
   if (!(p->gamma > 1.0) || !(p->Pr > 0.0) || !std::isfinite(p->gamma) || !std::isfinite(p->Pr)) return false;
@@ -597,7 +599,7 @@ struct tclbm_batch {
   std::vector<int64_t> steps;     // members' step counts the table's parity assumes
   int storage;
   hipStream_t stream;
-  KParams *d_tab;    // device table (src/dst of the even steps)
+  KParams *d_tab;    // device table: n entries for even steps, n with src/dst swapped
   int *d_start;      // device prefix sums of waves per member
   int total_waves;
   int graph_chunk;
@@ -624,7 +626,7 @@ static int batch_auto_rows(const tclbm_batch *b) {
 static hipError_t batch_upload(tclbm_batch *b) {
   const int n = (int)b->m.size();
   b->strip_rows = b->strip_rows_req > 0 ? b->strip_rows_req : batch_auto_rows(b);
-  std::vector<KParams> tab(n);
+  std::vector<KParams> tab(2 * n);  // [0, n): even steps; [n, 2n): odd steps (src, dst swapped)
   std::vector<int> start(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     tclbm_handle h = b->m[i];
@@ -635,10 +637,13 @@ static hipError_t batch_upload(tclbm_batch *b) {
     tab[i].strip_rows = rows;
     tab[i].n_strips = (h->k.ny + rows - 1) / rows;
     start[i + 1] = start[i] + tab[i].n_xtiles * tab[i].n_strips;
+    tab[n + i] = tab[i];
+    tab[n + i].src = tab[i].dst;
+    tab[n + i].dst = const_cast<void *>(tab[i].src);
   }
   b->total_waves = start[n];
   b->parity = 0;
-  hipError_t e = hipMemcpy(b->d_tab, tab.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(b->d_tab, tab.data(), sizeof(KParams) * 2 * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_start, start.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
   return e;
 }
@@ -694,7 +699,7 @@ tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_ha
   b->stream = members[0]->stream;
   b->graph_chunk = 16;
   b->strip_rows_req = 0;
-  hipError_t e = hipMalloc(&b->d_tab, sizeof(KParams) * n);
+  hipError_t e = hipMalloc(&b->d_tab, sizeof(KParams) * 2 * n);
   if (e == hipSuccess) e = hipMalloc(&b->d_start, sizeof(int) * (n + 1));
   if (e == hipSuccess) e = batch_upload(b);
   if (e != hipSuccess) {

@@ -33,6 +33,19 @@ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // ---------------------------------------------------------------- storage ---
+// 16-bit stores round stochastically, without bias, and deterministically:
+// the random bits are a hash of the value being stored and of its slot (plane
+// and node).  Round-to-nearest freezes a stored value whose per-step change is
+// below half a unit in the last place, which biases slow dynamics (with it,
+// BF16 Rayleigh-Benard runs never left the conduction state).  The hash is
+// multiplicative (Knuth): the top `nbits` of (v ^ slot*phi) * c, which depend
+// on every input bit.  The result depends only on the stored value and the
+// slot, so it is the same for any launch shape or batch composition.
+template <int nbits>
+__device__ __forceinline__ unsigned sr_bits(unsigned v, unsigned slot) {
+  return ((v ^ (slot * 0x9E3779B9u)) * 0x85EBCA6Bu) >> (32 - nbits);
+}
+
 template <int S>
 struct Store;
 template <>
@@ -40,38 +53,48 @@ struct Store<kF32> {
   using T = float;
   static __device__ __forceinline__ float ld(const T *p, long long i) { return p[i]; }
   static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = v; }
+  static __device__ __forceinline__ T enc(float v, unsigned) { return v; }
 };
 template <>
 struct Store<kF64> {
   using T = double;
   static __device__ __forceinline__ double ld(const T *p, long long i) { return p[i]; }
   static __device__ __forceinline__ void st(T *p, long long i, double v) { p[i] = v; }
+  static __device__ __forceinline__ T enc(double v, unsigned) { return v; }
 };
 template <>
 struct Store<kF16> {
-  // IEEE half of the deviation times 2^10, round to nearest even.  The power
-  // of two scales exactly; it moves half's normal range (6.1e-5 .. 65504) to
-  // deviations 6.0e-8 .. 64, so the tiny perturbations from which an
-  // instability grows keep 11 significant bits instead of falling into
-  // subnormals.  |deviation| >= 64 overflows to inf (reported as unstable).
+  // IEEE half of the deviation times 2^10.  The power of two scales exactly;
+  // it moves half's normal range (6.1e-5 .. 65504) to deviations 6.0e-8 .. 64,
+  // so the tiny perturbations from which an instability grows keep 11
+  // significant bits instead of falling into subnormals.  |deviation| >= 64
+  // overflows to inf (reported as unstable).  Stochastic rounding: random
+  // bits below half's last place are added to the FP32 pattern, which is then
+  // cut to half precision (exact for normal halfs).
   using T = unsigned short;
   static __device__ __forceinline__ float ld(const T *p, long long i) {
     return __half2float(__ushort_as_half(p[i])) * 0x1p-10f;
   }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) {
-    p[i] = __half_as_ushort(__float2half_rn(v * 0x1p10f));
+  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = enc(v, (unsigned)i); }
+  static __device__ __forceinline__ T enc(float v, unsigned slot) {
+    unsigned b = __float_as_uint(v * 0x1p10f);
+    b = (b + sr_bits<13>(b, slot)) & ~0x1FFFu;
+    return __half_as_ushort(__float2half_rn(__uint_as_float(b)));
   }
 };
 template <>
-struct Store<kBF16> {  // bfloat16, round to nearest even
+struct Store<kBF16> {  // bfloat16: the upper half of the FP32 pattern, stochastic rounding
   using T = unsigned short;
   static __device__ __forceinline__ float ld(const T *p, long long i) {
     return __bfloat162float(__ushort_as_bfloat16(p[i]));
   }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) {
-    p[i] = __bfloat16_as_ushort(__float2bfloat16(v));
+  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = enc(v, (unsigned)i); }
+  static __device__ __forceinline__ T enc(float v, unsigned slot) {
+    const unsigned b = __float_as_uint(v);
+    return (T)((b + sr_bits<16>(b, slot)) >> 16);
   }
 };
+
 
 template <int S>
 struct Real {
@@ -407,8 +430,9 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    Store<S>::st(dst + a * k.plane, own, P[a]);
-    if (k.thermal) Store<S>::st(dst + (a + 9) * k.plane, own, Q[a]);
+    const unsigned slot_f = (unsigned)(a * k.plane) + own, slot_h = (unsigned)((a + 9) * k.plane) + own;
+    (dst + a * k.plane)[own] = Store<S>::enc(P[a], slot_f);
+    if (k.thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], slot_h);
   }
 }
 
@@ -418,11 +442,12 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 constexpr int kStepWaves = 4;
 
 // Build-time launch shape of the step kernels (defaults chosen by measurement).
+
 #ifndef TCLBM_PREFETCH
 #define TCLBM_PREFETCH 0
 #endif
 #ifndef TCLBM_WAVES_PER_EU
-#define TCLBM_WAVES_PER_EU 0
+#define TCLBM_WAVES_PER_EU 3
 #endif
 #if TCLBM_WAVES_PER_EU > 0
 #define TCLBM_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_WAVES_PER_EU, TCLBM_WAVES_PER_EU)))
@@ -542,15 +567,28 @@ __global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void step_kernel(KParams
   if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
   march<S>(k, wave, threadIdx.x & 63);
 }
+__global__ __launch_bounds__(64 * kStepWaves) void step_kernel_f64(KParams k) {
+  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  if (wave >= k.n_xtiles * k.n_strips) return;
+  march<kF64>(k, wave, threadIdx.x & 63);
+}
 
 // Batched step: one launch advances every lattice of a table by one step.
 // wave_start[i] is the first global wave of instance i (prefix sum of
 // n_xtiles * n_strips, wave_start[n] = total); waves of one instance are
-// contiguous, ordered as the table (the autotuner orders the table).
+// contiguous, in table order (largest lattices first).
+#ifndef TCLBM_BATCH_WAVES_PER_EU
+#define TCLBM_BATCH_WAVES_PER_EU 3
+#endif
+#if TCLBM_BATCH_WAVES_PER_EU > 0
+#define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
+#else
+#define TCLBM_BATCH_OCC
+#endif
+
 template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void batch_step_kernel(const KParams *__restrict__ tab,
-                                                                     const int *__restrict__ wave_start,
-                                                                     int n_inst, int parity) {
+__device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, const int *__restrict__ wave_start,
+                                           int n_inst, int parity) {
   const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
   if (wave >= wave_start[n_inst]) return;
   int lo = 0, hi = n_inst - 1;  // last instance whose start <= wave
@@ -560,13 +598,22 @@ __global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void batch_step_kernel(c
     else hi = mid - 1;
   }
   lo = __builtin_amdgcn_readfirstlane(lo);
-  KParams k = tab[lo];
-  if (parity) {  // odd steps run from the second buffer
-    const void *t = k.src;
-    k.src = k.dst;
-    k.dst = const_cast<void *>(t);
-  }
-  march<S>(k, wave - wave_start[lo], threadIdx.x & 63);
+  // the table holds each member twice: entries [0, n) for even steps and
+  // [n, 2n) with source and destination swapped for odd steps; the
+  // descriptor is read in place (like a kernel argument), not copied
+  march<S>(tab[parity * n_inst + lo], wave - wave_start[lo], threadIdx.x & 63);
+}
+
+// 32- and 16-bit storage may take a register cap (occupancy); FP64 never does
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH_OCC void batch_step_kernel(
+    const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity) {
+  batch_body<S>(tab, wave_start, n_inst, parity);
+}
+__global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel_f64(const KParams *__restrict__ tab,
+                                                                         const int *__restrict__ wave_start,
+                                                                         int n_inst, int parity) {
+  batch_body<kF64>(tab, wave_start, n_inst, parity);
 }
 
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
@@ -578,7 +625,7 @@ hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int 
     case kF32: hipLaunchKernelGGL(batch_step_kernel<kF32>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
     case kF16: hipLaunchKernelGGL(batch_step_kernel<kF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
     case kBF16: hipLaunchKernelGGL(batch_step_kernel<kBF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
-    case kF64: hipLaunchKernelGGL(batch_step_kernel<kF64>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    case kF64: hipLaunchKernelGGL(batch_step_kernel_f64, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -594,7 +641,7 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
     case kF32: hipLaunchKernelGGL(step_kernel<kF32>, grid, block, 0, s, k); break;
     case kF16: hipLaunchKernelGGL(step_kernel<kF16>, grid, block, 0, s, k); break;
     case kBF16: hipLaunchKernelGGL(step_kernel<kBF16>, grid, block, 0, s, k); break;
-    case kF64: hipLaunchKernelGGL(step_kernel<kF64>, grid, block, 0, s, k); break;
+    case kF64: hipLaunchKernelGGL(step_kernel_f64, grid, block, 0, s, k); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
