@@ -89,7 +89,7 @@ int pitch_of(const tclbm_params *p) { return (int)up((size_t)p->nx, 64); }
 int planes_of(const tclbm_params *p) { return p->thermal ? 18 : 9; }
 
 struct Plan {
-  size_t buf, ref, acc, part, total;
+  size_t buf, ref, acc, part, ctr, total;
 };
 
 Plan plan_of(const tclbm_params *p) {
@@ -102,7 +102,8 @@ Plan plan_of(const tclbm_params *p) {
   pl.acc = p->accel_field ? up(2 * plane * rsz, kAlign) : 0;
   const long long n = (long long)p->nx * p->ny;
   pl.part = up(sizeof(double) * kNumSums * (size_t)((n + 255) / 256), kAlign);
-  pl.total = 2 * pl.buf + pl.ref + pl.acc + pl.part;
+  pl.ctr = kAlign;  // two 32-bit step counters
+  pl.total = 2 * pl.buf + pl.ref + pl.acc + pl.part + pl.ctr;
   return pl;
 }
 
@@ -218,6 +219,7 @@ tclbm_status launch_steps(tclbm_ctx *c, int64_t n) {
     KParams k = c->k;
     k.src = c->buf[c->cur];
     k.dst = c->buf[1 - c->cur];
+    k.par = c->cur;
     HIP_TRY(c, launch_step(k, c->p.storage, c->stream));
     c->cur = 1 - c->cur;
     ++c->steps;
@@ -239,6 +241,7 @@ tclbm_status build_graph(tclbm_ctx *c) {
     KParams k = c->k;
     k.src = c->buf[s & 1];
     k.dst = c->buf[1 - (s & 1)];
+    k.par = s & 1;
     lerr = launch_step(k, c->p.storage, c->stream);
   }
   hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -346,6 +349,7 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
   const size_t rsz = (p->storage == kF64) ? 8 : 4;
   char *acc = c->base + 2 * pl.buf + pl.ref;
   c->partials = reinterpret_cast<double *>(acc + pl.acc);
+  unsigned *ctr = reinterpret_cast<unsigned *>(acc + pl.acc + pl.part);
   c->nparts = (int)((n + 255) / 256);
   c->cur = 0;
   c->graph_chunk = 32;
@@ -353,6 +357,7 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
   c->k.rowref = refs;
   c->k.shiftF = refs + rsz * 2 * p->ny;
   c->k.shiftH = refs + rsz * (2 + 9) * p->ny;
+  c->k.ctr = ctr;
   decompose(c);
 
   tclbm_status st = TCLBM_OK;
@@ -371,6 +376,7 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
       e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
+    if (e == hipSuccess) e = hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned), c->stream);
     if (e != hipSuccess) { set_err(c, "ref upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
     if (p->accel_field) {
       const size_t plane = (size_t)c->k.plane;
@@ -633,6 +639,7 @@ static hipError_t batch_upload(tclbm_batch *b) {
     tab[i] = h->k;
     tab[i].src = h->buf[h->cur];
     tab[i].dst = h->buf[1 - h->cur];
+    tab[i].par = h->cur;
     const int rows = b->strip_rows < h->k.ny ? b->strip_rows : h->k.ny;
     tab[i].strip_rows = rows;
     tab[i].n_strips = (h->k.ny + rows - 1) / rows;
@@ -640,6 +647,7 @@ static hipError_t batch_upload(tclbm_batch *b) {
     tab[n + i] = tab[i];
     tab[n + i].src = tab[i].dst;
     tab[n + i].dst = const_cast<void *>(tab[i].src);
+    tab[n + i].par = 1 - h->cur;
   }
   b->total_waves = start[n];
   b->parity = 0;

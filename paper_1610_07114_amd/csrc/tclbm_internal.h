@@ -31,6 +31,11 @@ struct KParams {
   const void *rowref, *shiftF, *shiftH;
   // march decomposition
   int tile_w, lane_off, n_xtiles, strip_rows, n_strips;
+  // step counter of the lattice (16-bit stochastic rounding): ctr[par] holds
+  // the number of the step this launch computes, where par is the index of
+  // the source buffer; the launch writes ctr[1 - par] = ctr[par] + 1
+  unsigned *ctr;
+  int par;
 };
 
 // Reduction record written per block by the moments kernel.

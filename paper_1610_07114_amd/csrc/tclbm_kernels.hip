@@ -33,18 +33,31 @@ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // ---------------------------------------------------------------- storage ---
-// 16-bit stores round stochastically, without bias, and deterministically:
-// the random bits are a hash of the value being stored and of its slot (plane
-// and node).  Round-to-nearest freezes a stored value whose per-step change is
-// below half a unit in the last place, which biases slow dynamics (with it,
-// BF16 Rayleigh-Benard runs never left the conduction state).  The hash is
-// multiplicative (Knuth): the top `nbits` of (v ^ slot*phi) * c, which depend
-// on every input bit.  The result depends only on the stored value and the
-// slot, so it is the same for any launch shape or batch composition.
-template <int nbits>
-__device__ __forceinline__ unsigned sr_bits(unsigned v, unsigned slot) {
-  return ((v ^ (slot * 0x9E3779B9u)) * 0x85EBCA6Bu) >> (32 - nbits);
+// 16-bit stores round stochastically and without bias: random bits below the
+// target's last place are added to the FP32 pattern, which is then cut.  The
+// bits come from a counter-based generator keyed by (step, node, plane), never
+// by the value being rounded (bits derived from the value itself made the
+// rounding of a slowly varying value a fixed rule with a bias: a thermal
+// Couette flow then heated up and blew up).  Round-to-nearest freezes a stored
+// value whose per-step change is below half a unit in the last place (with
+// it, BF16 Rayleigh-Benard runs never left the conduction state).  Per node,
+// the "lowbias32" integer hash (C. Wellons' hash-prospector) of the node
+// index and the step; per plane, a multiplicative spread of that word.  The
+// result depends only on (step, node, plane), so it is the same for any
+// launch shape or batch composition.
+__device__ __forceinline__ unsigned sr_node(unsigned node, unsigned step) {
+  unsigned x = node ^ (step * 0x9E3779B9u);
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
 }
+__device__ __forceinline__ unsigned sr_word(unsigned hn, int plane) {
+  return (hn ^ ((unsigned)plane * 0x632BE5ABu)) * 0x85EBCA6Bu;  // use the top bits
+}
+constexpr unsigned kInitStep = 0xFFFFFFFFu;  // generator step of the initial state
 
 template <int S>
 struct Store;
@@ -52,14 +65,14 @@ template <>
 struct Store<kF32> {
   using T = float;
   static __device__ __forceinline__ float ld(const T *p, long long i) { return p[i]; }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = v; }
+  static __device__ __forceinline__ void st(T *p, long long i, float v, unsigned) { p[i] = v; }
   static __device__ __forceinline__ T enc(float v, unsigned) { return v; }
 };
 template <>
 struct Store<kF64> {
   using T = double;
   static __device__ __forceinline__ double ld(const T *p, long long i) { return p[i]; }
-  static __device__ __forceinline__ void st(T *p, long long i, double v) { p[i] = v; }
+  static __device__ __forceinline__ void st(T *p, long long i, double v, unsigned) { p[i] = v; }
   static __device__ __forceinline__ T enc(double v, unsigned) { return v; }
 };
 template <>
@@ -75,10 +88,11 @@ struct Store<kF16> {
   static __device__ __forceinline__ float ld(const T *p, long long i) {
     return __half2float(__ushort_as_half(p[i])) * 0x1p-10f;
   }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = enc(v, (unsigned)i); }
-  static __device__ __forceinline__ T enc(float v, unsigned slot) {
+  static __device__ __forceinline__ void st(T *p, long long i, float v, unsigned rnd) { p[i] = enc(v, rnd); }
+  // rnd: 32 random bits, of which the top 13 are used
+  static __device__ __forceinline__ T enc(float v, unsigned rnd) {
     unsigned b = __float_as_uint(v * 0x1p10f);
-    b = (b + sr_bits<13>(b, slot)) & ~0x1FFFu;
+    b = (b + (rnd >> 19)) & ~0x1FFFu;
     return __half_as_ushort(__float2half_rn(__uint_as_float(b)));
   }
 };
@@ -88,10 +102,11 @@ struct Store<kBF16> {  // bfloat16: the upper half of the FP32 pattern, stochast
   static __device__ __forceinline__ float ld(const T *p, long long i) {
     return __bfloat162float(__ushort_as_bfloat16(p[i]));
   }
-  static __device__ __forceinline__ void st(T *p, long long i, float v) { p[i] = enc(v, (unsigned)i); }
-  static __device__ __forceinline__ T enc(float v, unsigned slot) {
+  static __device__ __forceinline__ void st(T *p, long long i, float v, unsigned rnd) { p[i] = enc(v, rnd); }
+  // rnd: 32 random bits, of which the top 16 are used
+  static __device__ __forceinline__ T enc(float v, unsigned rnd) {
     const unsigned b = __float_as_uint(v);
-    return (T)((b + sr_bits<16>(b, slot)) >> 16);
+    return (T)((b + (rnd >> 16)) >> 16);
   }
 };
 
@@ -417,7 +432,7 @@ __device__ __forceinline__ R ddx(const KParams &k, R q, int xl) {
 template <int S>
 __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                               const Col &col, bool store, const RowState<typename Real<S>::T> &s,
-                                              typename Real<S>::T Dy, int xl) {
+                                              typename Real<S>::T Dy, int xl, unsigned step) {
   using R = typename Real<S>::T;
   using ST = typename Store<S>::T;
   const R Dx = ddx<R>(k, s.qx, xl);
@@ -428,11 +443,11 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   if (!store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
   const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
+  const unsigned hn = (S == kF16 || S == kBF16) ? sr_node(own, step) : 0u;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    const unsigned slot_f = (unsigned)(a * k.plane) + own, slot_h = (unsigned)((a + 9) * k.plane) + own;
-    (dst + a * k.plane)[own] = Store<S>::enc(P[a], slot_f);
-    if (k.thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], slot_h);
+    (dst + a * k.plane)[own] = Store<S>::enc(P[a], sr_word(hn, a));
+    if (k.thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], sr_word(hn, a + 9));
   }
 }
 
@@ -473,6 +488,11 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
   RowState<R> cur, nxt;
   R qy_m1 = R(0), qy_m2 = R(0);
   int j;
+  // step number for the 16-bit rounding generator; the lattice's first wave
+  // advances the counter for the next launch (the other cell: no race)
+  constexpr bool k16 = (S == kF16 || S == kBF16);
+  const unsigned step = k16 ? k.ctr[k.par] : 0u;
+  if (k16 && wave == 0 && lane == 0) k.ctr[1 - k.par] = step + 1u;
   if (r1 - r0 == 1 && (yper || (r0 >= 3 && r0 <= ny - 4))) {
     // single-row strip away from the edges (small lattices): the three rows it
     // needs are independent, so all their loads are issued before any is used
@@ -490,7 +510,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
     cur.q = row_ref(k, c, r0);
     pull_shift<S>(k, r0, col, cur.f, cur.h);
     finish(k, c, r0, col.xc, cur);
-    collide_store<S>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl);
+    collide_store<S>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl, step);
     return;
   }
   if (!yper && r0 == 0) {
@@ -502,7 +522,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
     if (is_wall_row(k, 0)) get_wall_row<S>(k, c, 0, col, nxt, cur);
     else get_row<S>(k, c, 0, col, cur);
     const R Dy = R(0.5) * (R(-3) * cur.qy + R(4) * nxt.qy - two.qy);
-    collide_store<S>(k, c, 0, col, store, cur, Dy, xl);
+    collide_store<S>(k, c, 0, col, store, cur, Dy, xl, step);
     qy_m1 = cur.qy;
     cur = nxt;
     j = 1;
@@ -536,7 +556,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
   for (; j < r1; ++j) {
     if (!yper && j == ny - 1) {  // top edge: one-sided difference with the rows below
       const R Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_m1 + qy_m2);
-      collide_store<S>(k, c, j, col, store, cur, Dy, xl);
+      collide_store<S>(k, c, j, col, store, cur, Dy, xl, step);
       break;
     }
     const int yn = (j == ny - 1) ? 0 : j + 1;
@@ -554,7 +574,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
       }
     }
     const R Dy = R(0.5) * (nxt.qy - qy_m1);
-    collide_store<S>(k, c, j, col, store, cur, Dy, xl);
+    collide_store<S>(k, c, j, col, store, cur, Dy, xl, step);
     qy_m2 = qy_m1;
     qy_m1 = cur.qy;
     cur = nxt;
@@ -562,9 +582,17 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
 }
 
 template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void step_kernel(KParams k) {
+__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
   const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
   if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
+  march<S>(k, wave, threadIdx.x & 63);
+}
+// 16-bit storage: the stochastic-rounding stores need a few more registers;
+// capped to keep 3 waves per SIMD (a handful of spills)
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void step_kernel_16(KParams k) {
+  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  if (wave >= k.n_xtiles * k.n_strips) return;
   march<S>(k, wave, threadIdx.x & 63);
 }
 __global__ __launch_bounds__(64 * kStepWaves) void step_kernel_f64(KParams k) {
@@ -639,8 +667,8 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
   dim3 grid(blocks), block(64 * kStepWaves);
   switch (storage) {
     case kF32: hipLaunchKernelGGL(step_kernel<kF32>, grid, block, 0, s, k); break;
-    case kF16: hipLaunchKernelGGL(step_kernel<kF16>, grid, block, 0, s, k); break;
-    case kBF16: hipLaunchKernelGGL(step_kernel<kBF16>, grid, block, 0, s, k); break;
+    case kF16: hipLaunchKernelGGL(step_kernel_16<kF16>, grid, block, 0, s, k); break;
+    case kBF16: hipLaunchKernelGGL(step_kernel_16<kBF16>, grid, block, 0, s, k); break;
     case kF64: hipLaunchKernelGGL(step_kernel_f64, grid, block, 0, s, k); break;
     default: return hipErrorInvalidValue;
   }
@@ -706,12 +734,13 @@ __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho,
       shf = reinterpret_cast<const R *>(k.shiftF)[9 * ty + a];
       shh = reinterpret_cast<const R *>(k.shiftH)[9 * ty + a];
     }
-    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp] - shf);
+    const unsigned hn = sr_node((unsigned)own, kInitStep);
+    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp] - shf, sr_word(hn, a));
     if (k.thermal) {
       const R E = R(0.5) * (c.b * th + vx * vx + vy * vy);
       const R sg = drho * E + q.rho * (R(0.5) * c.b * dth + R(0.5) * (vx * vx + vy * vy));
       heq_dev(c, q, drho, vx, vy, dth, sg, he);
-      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp] - shh);
+      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp] - shh, sr_word(hn, a + 9));
     }
   }
 }

@@ -45,7 +45,11 @@ class Request:
     def case(self) -> W.Case:
         if self.kind == "rb":
             return W.rayleigh_benard(nx=self.nx, ny=self.ny, Ra=self.Ra, Pr=self.Pr, seed=self.seed)
-        return W.couette(nx=self.nx, ny=self.ny, u0=0.05, Pr=self.Pr)
+        # w2 = w3 = w4 = 1 as in the paper's other thermal cases: its Couette
+        # set (1.1, 1.6, 0.3) is unstable to 2-D perturbations, which a
+        # Couette lattice wider than it is periodic only escapes while it
+        # stays exactly 1-D
+        return W.couette(nx=self.nx, ny=self.ny, u0=0.05, Pr=self.Pr, w2=1.0, w3=1.0, w4=1.0)
 
 
 def solve_steps(kind: str, ny: int, time_units: float) -> int:

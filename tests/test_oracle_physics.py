@@ -362,3 +362,24 @@ def test_rayleigh_benard_nusselt_table3():
         nus.append(Oc.nusselt(uy, T, case.T0, m["H"], m["kappa"], m["dT"]))
     assert max(nus) - min(nus) < 2e-3 * nus[-1]           # steady
     assert abs(nus[-1] - 2.661) / 2.661 < 0.06
+
+
+def test_couette_rate_set_is_unstable_in_2d():
+    """The thermal Couette case uses the rates w2, w3, w4 = 1.1, 1.6, 0.3 of
+    Section 5B.  The flow is exactly x-invariant, so a run never meets a 2-D
+    mode; seeded with a 1e-6 random 2-D perturbation it blows up, while the
+    same flow with w2 = w3 = w4 = 1 (the rates of the other thermal cases)
+    stays bounded.  Documents why the serving workload's Couette requests use
+    unit rates (stochastic 16-bit rounding perturbs every node differently)."""
+    rng = np.random.default_rng(0)
+    out = {}
+    for ws in ((1.1, 1.6, 0.3), (1.0, 1.0, 1.0)):
+        c = W.couette(nx=64, ny=32, u0=0.05, Pr=0.71, w2=ws[0], w3=ws[1], w4=ws[2])
+        c = c.with_(ux=c.ux + 1e-6 * rng.standard_normal(c.ux.shape),
+                    uy=c.uy + 1e-6 * rng.standard_normal(c.uy.shape))
+        _, _, v, T = oracle_lattice(c).step(1200).macros()
+        out[ws] = (np.abs(v).max(), np.abs(T - 1.01).max())
+    vp, tp = out[(1.1, 1.6, 0.3)]
+    assert not (np.isfinite(vp) and vp < 0.05)                  # blown up
+    v1, t1 = out[(1.0, 1.0, 1.0)]
+    assert v1 < 1e-3 and t1 < 0.02                              # bounded, decaying
