@@ -246,3 +246,53 @@ def test_batch_equals_members_alone_bitwise(T):
         assert lat.steps == 75
         assert np.array_equal(lat.read_state(), ref)
         lat.close()
+
+
+@pytest.mark.parametrize("nx,ny,walls,storage", [
+    (3, 3, False, "f64"),      # smallest periodic lattice: every neighbour wraps
+    (3, 5, True, "f64"),       # smallest walled lattice (one fluid row between walls and edges)
+    (63, 4, False, "f32"),     # one full 62-column tile plus a 1-column ragged tile
+    (125, 7, True, "f32"),     # ragged tile and rows not divisible by the strip height
+    (61, 9, False, "f64"),     # single tile of a non-periodic-x lattice (bounce-back ends)
+])
+def test_edge_shapes(T, nx, ny, walls, storage):
+    """Degenerate and ragged shapes against the oracle: lattices of 3 nodes
+    per side, a 1-column last tile, odd strip remainders, bounce-back x ends."""
+    case = W.uniform_noise(nx, ny, seed=nx + ny, ax=2e-5, ay=-1e-5, pointwise=1e-3)
+    if walls:
+        case = case.with_(bc=(W.PERIODIC, W.PERIODIC, W.WALL, W.WALL), wall_T=(1.0, 1.0, 1.01, 0.99),
+                          wall_ux=(0.0, 0.0, 0.0, 0.02))
+    if nx == 61:
+        case = case.with_(bc=(W.BOUNCEBACK, W.BOUNCEBACK, W.PERIODIC, W.PERIODIC))
+    say(f"case edge shape {nx}x{ny} walls={walls} {storage} 60 steps")
+    g, o, _ = run_pair(T, case, 60, storage=storage, tuning=(2, 0))
+    e = rel_err(g, o, case)
+    say(f"  errors {e}")
+    assert max(e.values()) < (1e-10 if storage == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_batch_equals_alone_other_storage(T, storage):
+    """The batched launch is bitwise neutral in FP64 and with 16-bit storage
+    (whose stochastic rounding is keyed by step, node and plane only)."""
+    import torch
+    cases = [W.rayleigh_benard(nx=130, ny=67, seed=3, noise=1e-3), W.uniform_noise(70, 33, seed=5, ax=1e-5),
+             W.shock_tube(nx=300, ny=5)]
+    say(f"case batch of 3 lattices {storage}, 41 steps, vs alone")
+    stream = torch.cuda.Stream()
+    alone = []
+    for cs in cases:
+        a = T.Lattice(cs, storage=storage, stream=stream)
+        a.step(41)
+        alone.append(a.read_state())
+        a.close()
+    lats = [T.Lattice(cs, storage=storage, stream=stream) for cs in cases]
+    b = T.Batch(lats)
+    b.set_graph_chunk(8)
+    b.step(20)
+    b.set_strip_rows(3)
+    b.step(21)
+    b.close()
+    for lat, ref in zip(lats, alone):
+        assert np.array_equal(lat.read_state(), ref)
+        lat.close()
