@@ -5,6 +5,7 @@ compare against.  Calls only the oracle and the seeded input generators.
   python tests/golden/make_nu_golden.py batch   # seeded subset of the batched RB workload
   python tests/golden/make_nu_golden.py rb512   # 512x256 Rayleigh-Benard, 2e5 steps
   python tests/golden/make_nu_golden.py fields  # final FP64 fields of the steady subset
+  python tests/golden/make_nu_golden.py onset   # kinetic-energy growth rates near Ra_c
 
 Nu follows the Section 5D definition (oracle.nusselt).  A run lasts 120 H/u_c
 (the batched subset) or 2e5 steps (512x256); Nu is sampled on a fixed step
@@ -42,6 +43,35 @@ def schedule(H: int, uc: float, total_tu: float = 120.0, window_tu: float = 10.0
     total = int(round(total_tu * tu / every)) * every
     avg_from = total - int(round(window_tu * tu / every)) * every
     return every, total, avg_from
+
+
+ONSET_RA = (1500.0, 1650.0, 1800.0, 1950.0)
+ONSET_NY = 51
+
+
+def onset_history(Ra):
+    """Kinetic energy (sum of rho u^2 / 2) every 1000 steps over 30000 steps of
+    the Section 5D setting (6% temperature difference, Pr 0.71) on a 2:1 box,
+    from a 1e-3 temperature perturbation (kept well above the FP32 rounding
+    floor of the decaying cases)."""
+    O.set_num_threads(2)
+    c = W.rayleigh_benard(nx=2 * ONSET_NY, ny=ONSET_NY, Ra=Ra, Pr=0.71, dT=0.06, seed=1, noise=1e-3)
+    from helpers import oracle_lattice
+    L = oracle_lattice(c)
+    ts, es = [], []
+    for _ in range(30):
+        L.step(1000)
+        r, u, v, _ = L.macros()
+        ts.append(L.steps)
+        es.append(float(np.sum(0.5 * r * (u * u + v * v))))
+    return ts, es
+
+
+def growth_rate(ts, es, t_from=10000):
+    """sigma = half the slope of ln(kinetic energy) over steps >= t_from."""
+    ts, le = np.asarray(ts, dtype=float), np.log(np.asarray(es))
+    m = ts >= t_from
+    return float(np.polyfit(ts[m], le[m], 1)[0] / 2)
 
 
 def final_fields(args):
@@ -129,6 +159,16 @@ def main():
         print(f"512x256: Nu(end) {h['nu'][-1]:.6f} mean {h['nu_mean']:.6f} unsteadiness {h['unsteadiness']:.2e} "
               f"({h['seconds']} s)", flush=True)
         path = os.path.join(HERE, "rb512x256_nu_fp64.json")
+    elif which == "onset":
+        with ProcessPoolExecutor(max_workers=4) as ex:
+            hist = list(ex.map(onset_history, ONSET_RA))
+        sig = [growth_rate(t, e) for t, e in hist]
+        p = np.polyfit(ONSET_RA, sig, 1)
+        out = dict(workload=f"rayleigh_benard {2 * ONSET_NY}x{ONSET_NY}, dT 0.06, Pr 0.71, seed 1, noise 1e-3",
+                   Ra=list(ONSET_RA), sigma=sig, Ra_c=float(-p[1] / p[0]),
+                   histories=[dict(steps=t, kinetic=e) for t, e in hist])
+        print("sigma", sig, "Ra_c", out["Ra_c"], flush=True)
+        path = os.path.join(HERE, "rb_onset_fp64.json")
     elif which == "fields":
         # final state of every batched instance whose Nu ended steady (window
         # variation < 2e-3): the start of the 16-bit steady-state checks

@@ -296,3 +296,55 @@ def test_batch_equals_alone_other_storage(T, storage):
     for lat, ref in zip(lats, alone):
         assert np.array_equal(lat.read_state(), ref)
         lat.close()
+
+
+@pytest.mark.slow
+def test_full_size_rb_8192x4096_vs_oracle(T):
+    """The HBM-resident workload bench.py times (8192 x 4096 Rayleigh-Benard,
+    FP32, automatic strip height, HIP-graph chunks of 32): every node against
+    the FP64 oracle after 10 steps."""
+    case = W.rayleigh_benard(nx=8192, ny=4096, Ra=1e5, Pr=0.71, seed=0)
+    say("case rayleigh-benard 8192x4096 fp32 10 steps (bench launch shape) vs oracle")
+    lat = T.Lattice(case, storage="f32")
+    lat.set_tuning(0, 32)
+    lat.step(10)
+    g = lat.moments()[:4]
+    lat.close()
+    o = oracle_lattice(case).step(10).macros()
+    e = rel_err(g, o, case)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+
+
+def test_full_batch_256_sampled_vs_alone_and_oracle(T):
+    """The batched workload as bench.py runs it (256 seeded lattices, one
+    launch per step, automatic strip height, graph chunks of 32): a seeded
+    sample of members equals the same lattices stepped alone, bitwise, and
+    the smallest member matches the FP64 oracle."""
+    import torch
+    specs = W.batched_rb_specs(256, seed=0)
+    cases = [W.rb_from_spec(s) for s in specs]
+    say("case batch of 256 lattices fp32, 40 steps, sampled members vs alone / oracle")
+    stream = torch.cuda.Stream()
+    lats = [T.Lattice(c, storage="f32", stream=stream) for c in cases]
+    b = T.Batch(lats)
+    b.set_graph_chunk(32)
+    b.step(40)
+    say(f"  strip rows in use {b.strip_rows}, waves {b.waves}")
+    b.close()
+    rng = np.random.default_rng(11)
+    sample = sorted(set(rng.choice(256, size=8, replace=False).tolist()) |
+                    {int(np.argmin([c.nx * c.ny for c in cases]))})
+    for i in sample:
+        a = T.Lattice(cases[i], storage="f32", stream=stream)
+        a.step(40)
+        assert np.array_equal(a.read_state(), lats[i].read_state()), f"member {i}"
+        a.close()
+    small = int(np.argmin([c.nx * c.ny for c in cases]))
+    g = lats[small].moments()[:4]
+    o = oracle_lattice(cases[small]).step(40).macros()
+    e = rel_err(g, o, cases[small])
+    say(f"  smallest member {cases[small].nx}x{cases[small].ny}: errors {e}")
+    assert max(e.values()) < 1e-5
+    for lat in lats:
+        lat.close()

@@ -248,3 +248,44 @@ def test_rb512_nusselt_vs_fp64(T, storage, tol):
     say(f"  Nu end {nus[-1]:.6f} vs {g['nu'][-1]:.6f} ({e_end:.2e}); mean {mean:.6f} vs {g['nu_mean']:.6f} "
         f"({e_mean:.2e})")
     assert e_mean < tol and e_end < tol
+
+
+def test_rb_onset_growth_rates_and_critical_rayleigh(T):
+    """Convective onset (Section 5D): four 102 x 51 lattices at Ra 1500-1950
+    (6% temperature difference, Pr 0.71, 1e-3 temperature noise) run as one
+    FP32 batch for 30000 steps; the kinetic-energy growth rates (steps
+    10000-30000) match the stored FP64 oracle rates
+    within 3% of their spread, and the linear extrapolation of sigma(Ra) to
+    zero gives Ra_c within 0.5% of the oracle's and within 3% of the linear
+    theory value 1707.76 quoted in Section 5D (the paper's own scheme: 1707.07
+    on 200 x 100)."""
+    import torch
+    from paper_1610_07114_amd import workloads as W
+    g = _golden("rb_onset_fp64.json")
+    say(f"case RB onset, Ra {g['Ra']}, 102x51 fp32 batch, 30000 steps")
+    stream = torch.cuda.Stream()
+    cases = [W.rayleigh_benard(nx=102, ny=51, Ra=Ra, Pr=0.71, dT=0.06, seed=1, noise=1e-3) for Ra in g["Ra"]]
+    lats = [T.Lattice(c, storage="f32", stream=stream) for c in cases]
+    b = T.Batch(lats)
+    b.set_graph_chunk(32)
+    hist = [[] for _ in cases]
+    for _ in range(30):
+        b.step(1000)
+        for k, lat in enumerate(lats):
+            _, _, _, _, s = lat.moments(fields=False)
+            hist[k].append(s.kinetic)
+    b.close()
+    for lat in lats:
+        lat.close()
+    ts = np.arange(1, 31) * 1000.0
+    m = ts >= 10000
+    sig = [float(np.polyfit(ts[m], np.log(np.array(h))[m], 1)[0] / 2) for h in hist]
+    p = np.polyfit(g["Ra"], sig, 1)
+    ra_c = -p[1] / p[0]
+    spread = max(g["sigma"]) - min(g["sigma"])
+    for Ra, s1, s0 in zip(g["Ra"], sig, g["sigma"]):
+        say(f"  Ra {Ra:.0f}: sigma {s1:.4e} vs FP64 {s0:.4e}")
+    say(f"  Ra_c {ra_c:.1f} vs FP64 {g['Ra_c']:.1f} (linear theory 1707.76)")
+    assert max(abs(a - b_) for a, b_ in zip(sig, g["sigma"])) < 0.03 * spread
+    assert abs(ra_c - g["Ra_c"]) / g["Ra_c"] < 5e-3
+    assert abs(ra_c - 1707.76) / 1707.76 < 0.03

@@ -383,3 +383,21 @@ def test_couette_rate_set_is_unstable_in_2d():
     assert not (np.isfinite(vp) and vp < 0.05)                  # blown up
     v1, t1 = out[(1.0, 1.0, 1.0)]
     assert v1 < 1e-3 and t1 < 0.02                              # bounded, decaying
+
+
+def test_rayleigh_benard_onset_bracket():
+    """Convective onset near the linear-theory Ra_c = 1707.76 (Section 5D):
+    on a 62 x 31 box at the paper's setting the kinetic energy of a 1e-4
+    perturbation decays at Ra = 1300 and grows at Ra = 2200 (log-slope over
+    steps 12000-24000)."""
+    slopes = {}
+    for Ra in (1300.0, 2200.0):
+        c = W.rayleigh_benard(nx=62, ny=31, Ra=Ra, Pr=0.71, dT=0.06, seed=1, noise=1e-4)
+        L = oracle_lattice(c).step(12000)
+        ks = []
+        for _ in range(4):
+            r, u, v, _ = L.macros()
+            ks.append(float(np.sum(0.5 * r * (u * u + v * v))))
+            L.step(4000)
+        slopes[Ra] = np.polyfit(np.arange(4) * 4000.0, np.log(ks), 1)[0]
+    assert slopes[1300.0] < 0 < slopes[2200.0]
