@@ -150,10 +150,10 @@ void decompose(tclbm_ctx *c) {
   k.n_xtiles = (k.nx + k.tile_w - 1) / k.tile_w;
   int rows = c->strip_rows_req;
   if (rows <= 0) {
-    // enough waves to fill 256 CUs several times over; long strips when the
-    // lattice is large (halo rows are re-pulled once per strip), short ones
-    // (down to a single row) when it is small
-    const long long target = 16384;
+    // enough waves to fill 256 CUs many times over: strips of a few rows when
+    // the lattice is large (halo rows are re-pulled once per strip, mostly
+    // from L2), down to a single row when it is small
+    const long long target = 65536;
     long long r = ((long long)k.ny * k.n_xtiles) / target;
     rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }

@@ -121,7 +121,29 @@ struct Real<kF64> {
 };
 
 // ------------------------------------------------------------- utilities ---
-template <class R>
+// Scheme variants of the march.  M = 0 reads every scheme switch from the
+// launch descriptor.  M = 1 is the default thermal scheme with its switches
+// fixed at compile time (thermal, with the correction term, continuous h^eq
+// moments, the two-rate energy update with its force source, the wall density
+// from the known populations, uniform acceleration): its pulls, collision and
+// stores are then straight-line code without uniform branches in between.
+__host__ __device__ inline bool default_scheme(const KParams &k) {
+  return k.thermal == 1 && k.correction == 1 && k.heq_mode == 0 && k.h_coll == 0 && k.h_force == 1 &&
+         k.wall_rho == 0 && k.axf == nullptr;
+}
+
+struct Flags {
+  int thermal, wall_rho;
+  bool field;  // per-node acceleration
+};
+
+template <int M>
+__device__ __forceinline__ Flags flags(const KParams &k) {
+  if (M == 1) return Flags{1, 0, false};
+  return Flags{k.thermal, k.wall_rho, k.axf != nullptr};
+}
+
+template <class R, int M = 0>
 __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   Consts<R> c;
   c.R_ = (R)k.R;
@@ -135,11 +157,11 @@ __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   c.inv_tau_hf = (R)k.inv_tau_hf;
   c.two_b = (R)(2.0 / k.b);
   c.inv_RT0 = (R)(1.0 / (k.R * k.T0));
-  c.thermal = k.thermal;
-  c.correction = k.correction;
-  c.heq_mode = k.heq_mode;
-  c.h_coll = k.h_coll;
-  c.h_force = k.h_force;
+  c.thermal = (M == 1) ? 1 : k.thermal;
+  c.correction = (M == 1) ? 1 : k.correction;
+  c.heq_mode = (M == 1) ? 0 : k.heq_mode;
+  c.h_coll = (M == 1) ? 0 : k.h_coll;
+  c.h_force = (M == 1) ? 1 : k.h_force;
   return c;
 }
 
@@ -181,9 +203,9 @@ __device__ __forceinline__ Col make_col(const KParams &k, int xl) {
   return c;
 }
 
-template <class R>
+template <class R, int M = 0>
 __device__ __forceinline__ void node_accel(const KParams &k, int y, int x, R &ax, R &ay) {
-  if (k.axf) {
+  if (flags<M>(k).field) {
     long long i = (long long)y * k.pitch + x;
     ax = reinterpret_cast<const R *>(k.axf)[i];
     ay = reinterpret_cast<const R *>(k.ayf)[i];
@@ -193,9 +215,21 @@ __device__ __forceinline__ void node_accel(const KParams &k, int y, int x, R &ax
   }
 }
 
+// The per-row tables (references and shifts) are written once at create and
+// only read by the step kernels: read them through the constant address space,
+// so that row-uniform reads become scalar loads instead of vector loads that
+// the compiler must order behind the kernel's own stores.
+template <class R>
+using ConstPtr = const __attribute__((address_space(4))) R *;
+
+template <class R>
+__device__ __forceinline__ ConstPtr<R> const_table(const void *p) {
+  return (ConstPtr<R>)(reinterpret_cast<const R *>(p));
+}
+
 template <class R>
 __device__ __forceinline__ RowRef<R> row_ref(const KParams &k, const Consts<R> &c, int y) {
-  const R *rr = reinterpret_cast<const R *>(k.rowref);
+  const ConstPtr<R> rr = const_table<R>(k.rowref);
   return make_ref<R>(rr[2 * y], rr[2 * y + 1], c.b, c.heq_mode);
 }
 
@@ -232,7 +266,7 @@ __device__ __forceinline__ RowSrc row_src(const KParams &k, int y) {
 // (col.xc, y), f_a = P_a(x - e_a), as stored (deviations of the source row).
 // Links from outside a non-periodic side bounce back halfway at rest,
 // f_a = P_opp(a)(x).  Interior tiles and rows take a select-free path.
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &col,
                                            typename Real<S>::T *f, typename Real<S>::T *h) {
   using ST = typename Store<S>::T;
@@ -246,7 +280,7 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
                            (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
       const ST *base = src + a * k.plane;
       f[a] = Store<S>::ld(base, off);
-      if (k.thermal) h[a] = Store<S>::ld(base + hoff, off);
+      if (flags<M>(k).thermal) h[a] = Store<S>::ld(base + hoff, off);
     }
     return;
   }
@@ -260,39 +294,87 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
     const ST *base = src + (bb ? kOpp[a] : a) * k.plane;
     const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
     f[a] = Store<S>::ld(base, off);
-    if (k.thermal) h[a] = Store<S>::ld(base + hoff, off);
+    if (flags<M>(k).thermal) h[a] = Store<S>::ld(base + hoff, off);
   }
 }
 
 // Phase 2: re-express the pulled deviations against this row's reference,
 // adding r_a(source row) - r_a(y) (bounced links stay in the row: the rest
 // state is symmetric, no shift).
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void pull_shift(const KParams &k, int y, const Col &col,
                                            typename Real<S>::T *f, typename Real<S>::T *h) {
   using R = typename Real<S>::T;
-  const R *shF = reinterpret_cast<const R *>(k.shiftF) + 9 * y;
-  const R *shH = reinterpret_cast<const R *>(k.shiftH) + 9 * y;
+  const ConstPtr<R> shF = const_table<R>(k.shiftF) + 9 * y;
+  const ConstPtr<R> shH = const_table<R>(k.shiftH) + 9 * y;
   const RowSrc rs = row_src(k, y);
+  // the table entries are read unconditionally (always in bounds) and applied
+  // by selection, so that their loads are not tied to branches
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     if (kEy[a] == 0) continue;
+    const R sfa = shF[a];
+    const R sha = flags<M>(k).thermal ? shH[a] : R(0);
     const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
     const bool oy = kEy[a] > 0 ? rs.outB : rs.outT;
     const bool bb = ox || oy;
-    if (!bb) {
-      f[a] += shF[a];
-      if (k.thermal) h[a] += shH[a];
-    }
+    f[a] += bb ? R(0) : sfa;
+    if (flags<M>(k).thermal) h[a] += bb ? R(0) : sha;
   }
 }
 
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
                                      typename Real<S>::T *f, typename Real<S>::T *h) {
-  pull_issue<S>(k, y, col, f, h);
-  pull_shift<S>(k, y, col, f, h);
+  pull_issue<S, M>(k, y, col, f, h);
+  pull_shift<S, M>(k, y, col, f, h);
 }
+
+// Asynchronous pulls (FP32 storage): the loads of a row go straight into a
+// per-wave LDS slot (one 64-lane line per plane) with global_load_lds, so the
+// wave keeps no registers for loads in flight and computes the previous row
+// meanwhile.  The compiler does not track these LDS writes: lds_wait_loads()
+// must separate the issue from the reads, and lds_wait_reads() the reads of a
+// slot from the next issue into it.
+using LdsF = __attribute__((address_space(3))) float;
+constexpr int kLdsSlot = 18 * 64;  // floats per slot: 18 planes x 64 lanes
+
+__device__ __forceinline__ void lds_wait_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void lds_wait_reads() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <int M>
+__device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Col &col, LdsF *slot) {
+  using GV = __attribute__((address_space(1))) const void;
+  using LV = __attribute__((address_space(3))) void;
+  const float *src = reinterpret_cast<const float *>(k.src);
+  const RowSrc rs = row_src(k, y);
+  const long long hoff = 9 * k.plane;
+  const bool th = flags<M>(k).thermal;
+  if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
+                           (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
+      const float *base = src + a * k.plane;
+      __builtin_amdgcn_global_load_lds((GV *)(base + off), (LV *)(slot + a * 64), 4, 0, 0);
+      if (th) __builtin_amdgcn_global_load_lds((GV *)(base + hoff + off), (LV *)(slot + (9 + a) * 64), 4, 0, 0);
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+    const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
+    const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
+    const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
+    const bool bb = ox || oy;
+    const float *base = src + (bb ? kOpp[a] : a) * k.plane;
+    const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
+    __builtin_amdgcn_global_load_lds((GV *)(base + off), (LV *)(slot + a * 64), 4, 0, 0);
+    if (th) __builtin_amdgcn_global_load_lds((GV *)(base + hoff + off), (LV *)(slot + (9 + a) * 64), 4, 0, 0);
+  }
+}
+
 
 // Populations of a WALL row node by non-equilibrium extrapolation from the
 // adjacent fluid node (I):
@@ -304,18 +386,19 @@ __device__ __forceinline__ void pull(const KParams &k, int y, const Col &col,
 // On entry dw holds the deviations pulled at the wall node; those that came
 // from the fluid and the tangential ones fix rho_w (default reading): with the
 // rest reference, k0 + 2 k_in = rho_r + the same combination of deviations.
-template <class R>
+template <class R, int M = 0>
 __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const RowRef<R> &qw,
                                           const RowRef<R> &qI, const R *dI, const R *gI, const Macro<R> &mI,
                                           R axI, R ayI, R axW, R ayW, R *dw, R *gw) {
   const R aI_n = (side == kYlo) ? -ayI : ayI;
   const R aW_n = (side == kYlo) ? -ayW : ayW;
   const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
-  const R thw = k.thermal ? c.R_ * (R)k.wall_T[side] : c.R_ * c.T0;
+  const Flags fl = flags<M>(k);
+  const R thw = fl.thermal ? c.R_ * (R)k.wall_T[side] : c.R_ * c.T0;
   R drw;
-  if (k.wall_rho == 1) {
+  if (fl.wall_rho == 1) {
     drw = mI.drho + (qI.rho - qw.rho);
-  } else if (k.wall_rho == 2) {
+  } else if (fl.wall_rho == 2) {
     drw = (mI.rho * mI.th + mI.rho * aI_n) / thw - qw.rho;
   } else {
     // bottom: links from the fluid are e_y = -1 (4, 7, 8); top: e_y = +1 (2, 5, 6)
@@ -333,7 +416,7 @@ __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, 
   source9(mI.rho, mI.ux, mI.uy, axI, ayI, sf);
 #pragma unroll
   for (int a = 0; a < 9; ++a) dw[a] = (ew[a] - ef[a]) - R(0.5) * (sw[a] - sf[a]) + dI[a];
-  if (k.thermal) {
+  if (fl.thermal) {
     const R Ew = R(0.5) * (c.b * thw + uwx * uwx + uwy * uwy);
     const R sgw = drw * Ew + qw.rho * (R(0.5) * c.b * dthw + R(0.5) * (uwx * uwx + uwy * uwy));
     heq_dev(c, qw, drw, uwx, uwy, dthw, sgw, ew);
@@ -351,10 +434,10 @@ struct RowState {
   R qx, qy;  // u (1 - theta)
 };
 
-template <class R>
+template <class R, int M = 0>
 __device__ __forceinline__ void finish(const KParams &k, const Consts<R> &c, int y, int xc, RowState<R> &s) {
   R ax, ay;
-  node_accel<R>(k, y, xc, ax, ay);
+  node_accel<R, M>(k, y, xc, ax, ay);
   s.m = macros(c, s.q, s.f, s.h, ax, ay);
   R om = R(1) - s.m.th * c.inv_RT0;
   s.qx = s.m.ux * om;
@@ -366,31 +449,31 @@ __device__ __forceinline__ bool is_wall_row(const KParams &k, int y) {
 }
 
 // State of row y (not a WALL row): pull and evaluate.
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void get_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                         const Col &col, RowState<typename Real<S>::T> &s) {
   s.q = row_ref(k, c, y);
-  pull<S>(k, y, col, s.f, s.h);
-  finish(k, c, y, col.xc, s);
+  pull<S, M>(k, y, col, s.f, s.h);
+  finish<typename Real<S>::T, M>(k, c, y, col.xc, s);
 }
 
-// State of row y (not a WALL row) from loads issued earlier by pull_issue.
-template <int S>
-__device__ __forceinline__ void get_row_raw(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
-                                            const Col &col, const typename Real<S>::T *rf,
-                                            const typename Real<S>::T *rh, RowState<typename Real<S>::T> &s) {
+// State of row y (not a WALL row) from a slot whose loads have landed.
+template <int M>
+__device__ __forceinline__ void get_row_lds(const KParams &k, const Consts<float> &c, int y, const Col &col,
+                                            const LdsF *slot, int lane, RowState<float> &s) {
   s.q = row_ref(k, c, y);
+  const bool th = flags<M>(k).thermal;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    s.f[a] = rf[a];
-    if (k.thermal) s.h[a] = rh[a];
+    s.f[a] = slot[a * 64 + lane];
+    if (th) s.h[a] = slot[(9 + a) * 64 + lane];
   }
-  pull_shift<S>(k, y, col, s.f, s.h);
-  finish(k, c, y, col.xc, s);
+  pull_shift<kF32, M>(k, y, col, s.f, s.h);
+  finish<float, M>(k, c, y, col.xc, s);
 }
 
 // State of the WALL row y whose fluid neighbour state is `in`.
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                              const Col &col, const RowState<typename Real<S>::T> &in,
                                              RowState<typename Real<S>::T> &s) {
@@ -398,12 +481,12 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   const int side = (y == 0) ? kYlo : kYhi;
   const int yf = (y == 0) ? 1 : y - 1;
   s.q = row_ref(k, c, y);
-  if (k.wall_rho == 0) pull<S>(k, y, col, s.f, s.h);
+  if (flags<M>(k).wall_rho == 0) pull<S, M>(k, y, col, s.f, s.h);
   R axI, ayI, axW, ayW;
-  node_accel<R>(k, yf, col.xc, axI, ayI);
-  node_accel<R>(k, y, col.xc, axW, ayW);
-  wall_node<R>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, s.f, s.h);
-  finish(k, c, y, col.xc, s);
+  node_accel<R, M>(k, yf, col.xc, axI, ayI);
+  node_accel<R, M>(k, y, col.xc, axW, ayW);
+  wall_node<R, M>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, s.f, s.h);
+  finish<R, M>(k, c, y, col.xc, s);
 }
 
 template <class R>
@@ -429,7 +512,7 @@ __device__ __forceinline__ R ddx(const KParams &k, R q, int xl) {
 }
 
 // Collide the current row and store it.
-template <int S>
+template <int S, int M = 0>
 __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                               const Col &col, bool store, const RowState<typename Real<S>::T> &s,
                                               typename Real<S>::T Dy, int xl, unsigned step) {
@@ -437,7 +520,7 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   using ST = typename Store<S>::T;
   const R Dx = ddx<R>(k, s.qx, xl);
   R ax, ay;
-  node_accel<R>(k, y, col.xc, ax, ay);
+  node_accel<R, M>(k, y, col.xc, ax, ay);
   R P[9], Q[9];
   collide(c, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
   if (!store) return;
@@ -447,7 +530,7 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     (dst + a * k.plane)[own] = Store<S>::enc(P[a], sr_word(hn, a));
-    if (k.thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], sr_word(hn, a + 9));
+    if (flags<M>(k).thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], sr_word(hn, a + 9));
   }
 }
 
@@ -458,8 +541,8 @@ constexpr int kStepWaves = 4;
 
 // Build-time launch shape of the step kernels (defaults chosen by measurement).
 
-#ifndef TCLBM_PREFETCH
-#define TCLBM_PREFETCH 0
+#ifndef TCLBM_LDS_PULL
+#define TCLBM_LDS_PULL 1
 #endif
 #ifndef TCLBM_WAVES_PER_EU
 #define TCLBM_WAVES_PER_EU 3
@@ -471,8 +554,8 @@ constexpr int kStepWaves = 4;
 #endif
 
 // The march of one wave over its (x tile, strip) of lattice k.
-template <int S>
-__device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
+template <int S, int M = 0>
+__device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF *lds) {
   using R = typename Real<S>::T;
   const int strip = wave / k.n_xtiles;
   const int xt = wave - strip * k.n_xtiles;
@@ -481,7 +564,7 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
   const int xl = xt * k.tile_w - k.lane_off + lane;
   const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
   const Col col = make_col(k, xl);
-  const Consts<R> c = make_consts<R>(k);
+  const Consts<R> c = make_consts<R, M>(k);
   const bool yper = (k.bc[kYlo] == kPeriodic);
   const int ny = k.ny;
 
@@ -498,107 +581,140 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane) {
     // needs are independent, so all their loads are issued before any is used
     const int ya = (r0 == 0) ? ny - 1 : r0 - 1, yb = (r0 == ny - 1) ? 0 : r0 + 1;
     RowState<R> lo, hi;
-    pull_issue<S>(k, ya, col, lo.f, lo.h);
-    pull_issue<S>(k, r0, col, cur.f, cur.h);
-    pull_issue<S>(k, yb, col, hi.f, hi.h);
+    pull_issue<S, M>(k, ya, col, lo.f, lo.h);
+    pull_issue<S, M>(k, r0, col, cur.f, cur.h);
+    pull_issue<S, M>(k, yb, col, hi.f, hi.h);
     lo.q = row_ref(k, c, ya);
-    pull_shift<S>(k, ya, col, lo.f, lo.h);
-    finish(k, c, ya, col.xc, lo);
+    pull_shift<S, M>(k, ya, col, lo.f, lo.h);
+    finish<R, M>(k, c, ya, col.xc, lo);
     hi.q = row_ref(k, c, yb);
-    pull_shift<S>(k, yb, col, hi.f, hi.h);
-    finish(k, c, yb, col.xc, hi);
+    pull_shift<S, M>(k, yb, col, hi.f, hi.h);
+    finish<R, M>(k, c, yb, col.xc, hi);
     cur.q = row_ref(k, c, r0);
-    pull_shift<S>(k, r0, col, cur.f, cur.h);
-    finish(k, c, r0, col.xc, cur);
-    collide_store<S>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl, step);
+    pull_shift<S, M>(k, r0, col, cur.f, cur.h);
+    finish<R, M>(k, c, r0, col.xc, cur);
+    collide_store<S, M>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl, step);
     return;
   }
   if (!yper && r0 == 0) {
     // bottom edge: row 0 needs u(1-theta) of rows 1 and 2 (one-sided difference)
-    get_row<S>(k, c, 1, col, nxt);                       // row 1 (ny >= 3: a fluid row)
+    get_row<S, M>(k, c, 1, col, nxt);                       // row 1 (ny >= 3: a fluid row)
     RowState<R> two;
-    if (is_wall_row(k, 2)) get_wall_row<S>(k, c, 2, col, nxt, two);
-    else get_row<S>(k, c, 2, col, two);
-    if (is_wall_row(k, 0)) get_wall_row<S>(k, c, 0, col, nxt, cur);
-    else get_row<S>(k, c, 0, col, cur);
+    if (is_wall_row(k, 2)) get_wall_row<S, M>(k, c, 2, col, nxt, two);
+    else get_row<S, M>(k, c, 2, col, two);
+    if (is_wall_row(k, 0)) get_wall_row<S, M>(k, c, 0, col, nxt, cur);
+    else get_row<S, M>(k, c, 0, col, cur);
     const R Dy = R(0.5) * (R(-3) * cur.qy + R(4) * nxt.qy - two.qy);
-    collide_store<S>(k, c, 0, col, store, cur, Dy, xl, step);
+    collide_store<S, M>(k, c, 0, col, store, cur, Dy, xl, step);
     qy_m1 = cur.qy;
     cur = nxt;
     j = 1;
   } else {
     const int ya = yper ? (r0 == 0 ? ny - 1 : r0 - 1) : r0 - 1;  // row below the strip
     if (!yper && ya == 0 && is_wall_row(k, 0)) {
-      get_row<S>(k, c, r0, col, cur);
-      get_wall_row<S>(k, c, 0, col, cur, nxt);
+      get_row<S, M>(k, c, r0, col, cur);
+      get_wall_row<S, M>(k, c, 0, col, cur, nxt);
       qy_m1 = nxt.qy;
     } else {
-      get_row<S>(k, c, ya, col, nxt);
+      get_row<S, M>(k, c, ya, col, nxt);
       qy_m1 = nxt.qy;
       if (!yper && r1 == ny && r0 >= 2) {
         // strip holds the top edge: also u(1-theta) two rows below its start
         RowState<R> low;
-        if (r0 - 2 == 0 && is_wall_row(k, 0)) get_wall_row<S>(k, c, 0, col, nxt, low);
-        else get_row<S>(k, c, r0 - 2, col, low);
+        if (r0 - 2 == 0 && is_wall_row(k, 0)) get_wall_row<S, M>(k, c, 0, col, nxt, low);
+        else get_row<S, M>(k, c, r0 - 2, col, low);
         qy_m2 = low.qy;
       }
-      if (is_wall_row(k, r0)) get_wall_row<S>(k, c, r0, col, nxt, cur);
-      else get_row<S>(k, c, r0, col, cur);
+      if (is_wall_row(k, r0)) get_wall_row<S, M>(k, c, r0, col, nxt, cur);
+      else get_row<S, M>(k, c, r0, col, cur);
     }
     j = r0;
   }
 
-  // Optional software pipeline: the loads of the row after next are issued
-  // before the current row's collision (costs 18 registers per lane).
-  R raw_f[9], raw_h[9];
-  bool have_raw = false;
-  constexpr bool kPrefetch = TCLBM_PREFETCH != 0;
+  // FP32 storage pipelines the pulls through two LDS slots: the row the next
+  // iteration needs is loaded while this one collides.
+  constexpr bool kAsync = (S == kF32) && TCLBM_LDS_PULL;
+  bool pending = false;  // the loads of row j + 1 are in lds slot `slot`
+  int slot = 0;
+  const auto next_pulled = [&](int jj) {
+    // row jj + 1 is pulled (not derived) by iteration jj of this strip
+    if (jj >= r1 || (!yper && jj == ny - 1)) return false;
+    const int y1 = (jj == ny - 1) ? 0 : jj + 1;
+    return yper || !is_wall_row(k, y1);
+  };
+  if (kAsync && next_pulled(j)) {
+    pull_issue_lds<M>(k, (j == ny - 1) ? 0 : j + 1, col, lds);
+    pending = true;
+  }
   for (; j < r1; ++j) {
     if (!yper && j == ny - 1) {  // top edge: one-sided difference with the rows below
       const R Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_m1 + qy_m2);
-      collide_store<S>(k, c, j, col, store, cur, Dy, xl, step);
+      collide_store<S, M>(k, c, j, col, store, cur, Dy, xl, step);
       break;
     }
     const int yn = (j == ny - 1) ? 0 : j + 1;
-    if (have_raw) get_row_raw<S>(k, c, yn, col, raw_f, raw_h, nxt);
-    else if (!yper && is_wall_row(k, yn)) get_wall_row<S>(k, c, yn, col, cur, nxt);
-    else get_row<S>(k, c, yn, col, nxt);
-    // prefetch the row the next iteration needs, unless it is the top edge
-    // (no row above) or a WALL row (derived, not pulled)
-    have_raw = false;
-    if (kPrefetch && j + 1 < r1 && (yper || yn != ny - 1)) {
-      const int ynn = (yn == ny - 1) ? 0 : yn + 1;
-      if (yper || !is_wall_row(k, ynn)) {
-        pull_issue<S>(k, ynn, col, raw_f, raw_h);
-        have_raw = true;
+    if constexpr (kAsync) {
+      if (pending) {
+        lds_wait_loads();
+        get_row_lds<M>(k, c, yn, col, lds + slot * kLdsSlot, lane, nxt);
+      } else if (!yper && is_wall_row(k, yn)) {
+        get_wall_row<S, M>(k, c, yn, col, cur, nxt);
+      } else {
+        get_row<S, M>(k, c, yn, col, nxt);
       }
+      pending = false;
+      if (next_pulled(j + 1)) {
+        // the other slot was last read an iteration ago
+        lds_wait_reads();
+        slot ^= 1;
+        pull_issue_lds<M>(k, (yn == ny - 1) ? 0 : yn + 1, col, lds + slot * kLdsSlot);
+        pending = true;
+      }
+    } else {
+      if (!yper && is_wall_row(k, yn)) get_wall_row<S, M>(k, c, yn, col, cur, nxt);
+      else get_row<S, M>(k, c, yn, col, nxt);
     }
     const R Dy = R(0.5) * (nxt.qy - qy_m1);
-    collide_store<S>(k, c, j, col, store, cur, Dy, xl, step);
+    collide_store<S, M>(k, c, j, col, store, cur, Dy, xl, step);
     qy_m2 = qy_m1;
     qy_m1 = cur.qy;
     cur = nxt;
   }
 }
 
-template <int S>
-__global__ __launch_bounds__(64 * kStepWaves) void step_kernel(KParams k) {
-  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+#ifndef TCLBM_SCHEME_SPECIAL
+#define TCLBM_SCHEME_SPECIAL 1
+#endif
+#ifndef TCLBM_F32_WAVES_PER_EU
+#define TCLBM_F32_WAVES_PER_EU 0
+#endif
+#if TCLBM_F32_WAVES_PER_EU > 0
+#define TCLBM_F32_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_F32_WAVES_PER_EU, TCLBM_F32_WAVES_PER_EU)))
+#else
+#define TCLBM_F32_OCC
+#endif
+
+template <int S, int M>
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_F32_OCC void step_kernel(KParams k) {
+  // wave-uniform: rows, strips and table reads stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
   if (wave >= k.n_xtiles * k.n_strips) return;  // whole wave leaves together
-  march<S>(k, wave, threadIdx.x & 63);
+  __shared__ float lds[kStepWaves * 2 * kLdsSlot];
+  march<S, M>(k, wave, threadIdx.x & 63, (LdsF *)(lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 2 * kLdsSlot));
 }
 // 16-bit storage: the stochastic-rounding stores need a few more registers;
 // capped to keep 3 waves per SIMD (a handful of spills)
-template <int S>
+template <int S, int M>
 __global__ __launch_bounds__(64 * kStepWaves) TCLBM_OCC void step_kernel_16(KParams k) {
-  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
   if (wave >= k.n_xtiles * k.n_strips) return;
-  march<S>(k, wave, threadIdx.x & 63);
+  march<S, M>(k, wave, threadIdx.x & 63, nullptr);
 }
+template <int M>
 __global__ __launch_bounds__(64 * kStepWaves) void step_kernel_f64(KParams k) {
-  const int wave = xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
   if (wave >= k.n_xtiles * k.n_strips) return;
-  march<kF64>(k, wave, threadIdx.x & 63);
+  march<kF64, M>(k, wave, threadIdx.x & 63, nullptr);
 }
 
 // Batched step: one launch advances every lattice of a table by one step.
@@ -629,7 +745,14 @@ __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, cons
   // the table holds each member twice: entries [0, n) for even steps and
   // [n, 2n) with source and destination swapped for odd steps; the
   // descriptor is read in place (like a kernel argument), not copied
-  march<S>(tab[parity * n_inst + lo], wave - wave_start[lo], threadIdx.x & 63);
+  const KParams &k = tab[parity * n_inst + lo];
+  LdsF *lds = nullptr;
+  if constexpr (S == kF32) {
+    __shared__ float buf[kStepWaves * 2 * kLdsSlot];
+    lds = (LdsF *)(buf + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 2 * kLdsSlot);
+  }
+  if (TCLBM_SCHEME_SPECIAL && default_scheme(k)) march<S, 1>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+  else march<S, 0>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
 }
 
 // 32- and 16-bit storage may take a register cap (occupancy); FP64 never does
@@ -665,11 +788,24 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
   const int waves = k.n_xtiles * k.n_strips;
   const int blocks = (waves + kStepWaves - 1) / kStepWaves;
   dim3 grid(blocks), block(64 * kStepWaves);
+  const bool d = TCLBM_SCHEME_SPECIAL && default_scheme(k);
   switch (storage) {
-    case kF32: hipLaunchKernelGGL(step_kernel<kF32>, grid, block, 0, s, k); break;
-    case kF16: hipLaunchKernelGGL(step_kernel_16<kF16>, grid, block, 0, s, k); break;
-    case kBF16: hipLaunchKernelGGL(step_kernel_16<kBF16>, grid, block, 0, s, k); break;
-    case kF64: hipLaunchKernelGGL(step_kernel_f64, grid, block, 0, s, k); break;
+    case kF32:
+      if (d) hipLaunchKernelGGL((step_kernel<kF32, 1>), grid, block, 0, s, k);
+      else hipLaunchKernelGGL((step_kernel<kF32, 0>), grid, block, 0, s, k);
+      break;
+    case kF16:
+      if (d) hipLaunchKernelGGL((step_kernel_16<kF16, 1>), grid, block, 0, s, k);
+      else hipLaunchKernelGGL((step_kernel_16<kF16, 0>), grid, block, 0, s, k);
+      break;
+    case kBF16:
+      if (d) hipLaunchKernelGGL((step_kernel_16<kBF16, 1>), grid, block, 0, s, k);
+      else hipLaunchKernelGGL((step_kernel_16<kBF16, 0>), grid, block, 0, s, k);
+      break;
+    case kF64:
+      if (d) hipLaunchKernelGGL((step_kernel_f64<1>), grid, block, 0, s, k);
+      else hipLaunchKernelGGL((step_kernel_f64<0>), grid, block, 0, s, k);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
