@@ -522,7 +522,7 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   R ax, ay;
   node_accel<R, M>(k, y, col.xc, ax, ay);
   R P[9], Q[9];
-  collide(c, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
+  collide<R, (S == kF32 || S == kF64)>(c, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
   if (!store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
   const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
