@@ -69,8 +69,17 @@ typedef enum { TCLBM_XLO = 0, TCLBM_XHI = 1, TCLBM_YLO = 2, TCLBM_YHI = 3 } tclb
 /* Boundary kinds.  PERIODIC must be set on both sides of an axis or neither.
  * BOUNCEBACK: halfway bounce-back at rest (adiabatic for h), any side.
  * WALL: node wall on the boundary row (y sides only) imposing (ux_w, uy_w, T_w)
- * by non-equilibrium extrapolation of both DFs from the adjacent fluid node. */
-typedef enum { TCLBM_BC_PERIODIC = 0, TCLBM_BC_BOUNCEBACK = 1, TCLBM_BC_WALL = 2 } tclbm_bc_kind;
+ * by non-equilibrium extrapolation of both DFs from the adjacent fluid node.
+ * WALL_ADIABATIC: as WALL for the velocity; the wall temperature is the one
+ * that makes the one-sided second-order normal derivative vanish,
+ * T_w = (4 T_1 - T_2)/3 from the nodes one and two rows inside (the fixed
+ * lower plate of the Couette test of Section 5B); needs ny >= 4. */
+typedef enum {
+  TCLBM_BC_PERIODIC = 0,
+  TCLBM_BC_BOUNCEBACK = 1,
+  TCLBM_BC_WALL = 2,
+  TCLBM_BC_WALL_ADIABATIC = 3
+} tclbm_bc_kind;
 
 typedef struct {
   int32_t nx, ny;        /* lattice size, each >= 3 */
@@ -100,6 +109,13 @@ typedef struct {
   int32_t bc[4];         /* tclbm_bc_kind per side (tclbm_side order); the
                             initial state is built for these boundaries */
   double wall_ux[4], wall_uy[4], wall_T[4];  /* WALL sides: imposed u and T */
+  int32_t viscosity_mode; /* 0: w1 = 1/tau_f everywhere (default); 1: dynamic
+                             viscosity mu = mu0 T/T0 (Section 5B): Eq. (29)
+                             with p = rho R T gives, per node,
+                             1/w1 = mu0/(rho R T0) + 1/2, and w_h, tau_hf follow
+                             from that w1 at constant Pr (tau_f is then unused) */
+  double mu0;             /* reference dynamic viscosity (> 0 when
+                             viscosity_mode = 1) */
 } tclbm_params;
 
 /* FP64 whole-lattice reductions of the state the next step would see

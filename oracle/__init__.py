@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tclbm_oracle.c")
 _LIB = os.path.join(_HERE, "libtclbm_oracle.so")
 
-PERIODIC, BOUNCEBACK, WALL = 0, 1, 2
+PERIODIC, BOUNCEBACK, WALL, WALL_ADIABATIC = 0, 1, 2, 3
 XLO, XHI, YLO, YHI = 0, 1, 2, 3
 
 
@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("wall_rho", ctypes.c_int32), ("heq_moments", ctypes.c_int32), ("h_collision", ctypes.c_int32),
         ("ax_field", ctypes.POINTER(ctypes.c_double)), ("ay_field", ctypes.POINTER(ctypes.c_double)),
         ("h_force", ctypes.c_int32),
+        ("viscosity_mode", ctypes.c_int32), ("mu0", ctypes.c_double),
     ]
 
 
@@ -194,6 +195,8 @@ class Params:
     heq_moments: int = 0
     h_collision: int = 0
     h_force: int = 1
+    viscosity_mode: int = 0   # 1: mu = mu0 T/T0 (Section 5B), per-node w1 from Eq. (29)
+    mu0: float = 0.0
     ax_field: Optional[np.ndarray] = None
     ay_field: Optional[np.ndarray] = None
     _keep: list = field(default_factory=list, repr=False)
@@ -201,7 +204,8 @@ class Params:
     def to_c(self) -> _Params:
         c = _Params()
         for name in ("nx", "ny", "R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay",
-                     "thermal", "correction", "wall_rho", "heq_moments", "h_collision", "h_force"):
+                     "thermal", "correction", "wall_rho", "heq_moments", "h_collision", "h_force",
+                     "viscosity_mode", "mu0"):
             setattr(c, name, getattr(self, name))
         for i in range(4):
             c.bc[i] = int(self.bc[i])

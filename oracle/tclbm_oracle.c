@@ -52,7 +52,16 @@
  *              form is kept as an option); no work term rho u.a is added to
  *              the total energy, as in Section 4;
  *   wall NEQ   the stored f is the transformed fbar, so the equilibrium part
- *              used in the extrapolation is f^eq - S/2 at each node.
+ *              used in the extrapolation is f^eq - S/2 at each node;
+ *   adiabatic  the fixed lower plate of the Couette test of Section 5B: a node
+ *              wall whose temperature makes the one-sided second-order normal
+ *              derivative vanish, T_w = (4 T_1 - T_2)/3 from the two nodes
+ *              inside, extrapolated like any other wall (T_w = T_1 leaks the
+ *              viscous heat of the first cell: 3% low bottom temperature at
+ *              H = 39);
+ *   mu(T)      mu = mu0 T/T0 of Section 5B enters through Eq. (29) at each node,
+ *              1/w1 = mu/p + 1/2 = mu0/(rho R T0) + 1/2, and w_h, tau_hf follow
+ *              from that w1 at constant Pr as everywhere else.
  *
  * Build:  gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -77,7 +86,9 @@ static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 enum { I00 = 0, I10, I01, IE, IN, IPI, I21, I12, I22 };
 
 /* Boundary kinds (one per side). */
-enum { ORC_PERIODIC = 0, ORC_BOUNCEBACK = 1, ORC_WALL = 2 };
+enum { ORC_PERIODIC = 0, ORC_BOUNCEBACK = 1, ORC_WALL = 2, ORC_WALL_ADIABATIC = 3 };
+
+static int is_wall(int kind) { return kind == ORC_WALL || kind == ORC_WALL_ADIABATIC; }
 enum { ORC_XLO = 0, ORC_XHI = 1, ORC_YLO = 2, ORC_YHI = 3 };
 
 typedef struct {
@@ -100,6 +111,8 @@ typedef struct {
   const double *ay_field;
   int32_t h_force;     /* energy DF body-force source: 1 the flux term (default),
                         * 0 none (Section 4 as printed) */
+  int32_t viscosity_mode; /* 0: w1 = 1/tau_f; 1: mu = mu0 T/T0 (Section 5B) */
+  double mu0;
 } orc_params;
 
 static double pw(double v, int n) {
@@ -325,6 +338,19 @@ static orc_derived derive(const orc_params *p) {
   return d;
 }
 
+/* The rates at a node of density rho.  Under mu = mu0 T/T0 (Section 5B),
+ * Eq. (29) with p = rho R T gives mu/p = mu0/(rho R T0): w1 depends on rho
+ * alone; w_h and tau_hf follow from it as in derive(). */
+static orc_derived derive_node(const orc_params *p, double rho) {
+  orc_derived d = derive(p);
+  if (p->viscosity_mode != 1) return d;
+  double mu_p = p->mu0 / (rho * p->R * p->T0);
+  d.w1 = 1.0 / (mu_p + 0.5);
+  d.wh = 1.0 / (mu_p / p->Pr + 0.5);
+  d.inv_tau_hf = d.w1 * (p->Pr - 1.0);
+  return d;
+}
+
 static double node_ax(const orc_params *p, long i) { return p->ax_field ? p->ax_field[i] : p->ax; }
 static double node_ay(const orc_params *p, long i) { return p->ay_field ? p->ay_field[i] : p->ay; }
 
@@ -361,7 +387,7 @@ void orc_node_macros(const orc_params *p, const double fb[9], const double hb[9]
 void orc_collide_node(const orc_params *p, const double fb[9], const double hb[9], double rho, double ux,
                       double uy, double T, double Dx, double Dy, double ax, double ay, double fout[9],
                       double hout[9]) {
-  orc_derived d = derive(p);
+  orc_derived d = derive_node(p, rho);
   double RT = p->R * T;
   if (!p->correction || !p->thermal) {
     Dx = 0.0;
@@ -491,7 +517,7 @@ static void wall_prestep(const orc_params *p, double *f, double *h) {
   const long n = (long)nx * ny;
   orc_derived d = derive(p);
   for (int side = ORC_YLO; side <= ORC_YHI; ++side) {
-    if (p->bc[side] != ORC_WALL) continue;
+    if (!is_wall(p->bc[side])) continue;
     int yb = (side == ORC_YLO) ? 0 : ny - 1;
     int yf = (side == ORC_YLO) ? 1 : ny - 2;
     for (int x = 0; x < nx; ++x) {
@@ -503,7 +529,20 @@ static void wall_prestep(const orc_params *p, double *f, double *h) {
       }
       double r, vx, vy, t;
       orc_node_macros(p, fb, hb, node_ax(p, i_f), node_ay(p, i_f), &r, &vx, &vy, &t);
-      double Tw = p->thermal ? p->wall_T[side] : p->T0;
+      double Tw = !p->thermal ? p->T0 : p->wall_T[side];
+      if (p->thermal && p->bc[side] == ORC_WALL_ADIABATIC) {
+        /* zero normal temperature gradient at the wall node, to second order:
+         * -3 T_w + 4 T_1 - T_2 = 0 with T_1, T_2 one and two nodes inside */
+        int y2 = (side == ORC_YLO) ? 2 : ny - 3;
+        long i2 = IDX(x, y2);
+        double f2[9], h2[9], r2, vx2, vy2, t2;
+        for (int a = 0; a < 9; ++a) {
+          f2[a] = f[a * n + i2];
+          h2[a] = h[a * n + i2];
+        }
+        orc_node_macros(p, f2, h2, node_ax(p, i2), node_ay(p, i2), &r2, &vx2, &vy2, &t2);
+        Tw = (4.0 * t - t2) / 3.0;
+      }
       /* wall pressure: the fluid neighbour's, carried one node along the
        * outward normal by the static momentum balance grad p = rho a */
       double an = (side == ORC_YLO) ? -node_ay(p, i_f) : node_ay(p, i_f);
@@ -559,11 +598,12 @@ int orc_check_params(const orc_params *p) {
   if (p->nx < 3 || p->ny < 3) return 1;
   if (!(p->tau_f > 0.5) || !(p->gamma > 1.0) || !(p->Pr > 0.0) || !(p->R > 0.0) || !(p->T0 > 0.0)) return 1;
   for (int s = 0; s < 4; ++s)
-    if (p->bc[s] < 0 || p->bc[s] > 2) return 1;
+    if (p->bc[s] < 0 || p->bc[s] > 3) return 1;
+  if (p->viscosity_mode < 0 || p->viscosity_mode > 1 || (p->viscosity_mode == 1 && !(p->mu0 > 0.0))) return 1;
   if (p->wall_rho < 0 || p->wall_rho > 2 || p->heq_moments < 0 || p->heq_moments > 1 || p->h_collision < 0 || p->h_collision > 1 || p->h_force < 0 || p->h_force > 1) return 1;
   if ((p->bc[ORC_XLO] == ORC_PERIODIC) != (p->bc[ORC_XHI] == ORC_PERIODIC)) return 1;
   if ((p->bc[ORC_YLO] == ORC_PERIODIC) != (p->bc[ORC_YHI] == ORC_PERIODIC)) return 1;
-  if (p->bc[ORC_XLO] == ORC_WALL || p->bc[ORC_XHI] == ORC_WALL) return 1; /* walls on y sides only */
+  if (is_wall(p->bc[ORC_XLO]) || is_wall(p->bc[ORC_XHI])) return 1; /* walls on y sides only */
   return 0;
 }
 

@@ -74,12 +74,16 @@ bool valid_params(const tclbm_params *p) {
   if (p->h_collision < 0 || p->h_collision > 1) return false;
   if (p->h_force < 0 || p->h_force > 1) return false;
   if (p->accel_field != 0 && p->accel_field != 1) return false;
+  if (p->viscosity_mode != 0 && p->viscosity_mode != 1) return false;
+  if (p->viscosity_mode == 1 && !(p->mu0 > 0.0 && std::isfinite(p->mu0))) return false;
   for (int q = 0; q < 4; ++q) {
-    if (p->bc[q] < kPeriodic || p->bc[q] > kWall) return false;
+    if (p->bc[q] < kPeriodic || p->bc[q] > kWallAdiabatic) return false;
     if (!(std::isfinite(p->wall_ux[q]) && std::isfinite(p->wall_uy[q]) && std::isfinite(p->wall_T[q]))) return false;
     if (p->bc[q] == kWall && !(p->wall_T[q] > 0)) return false;
+    // the adiabatic wall temperature uses the two rows inside the wall
+    if (p->bc[q] == kWallAdiabatic && p->ny < 4) return false;
   }
-  if (p->bc[kXlo] == kWall || p->bc[kXhi] == kWall) return false;
+  if (is_wall_kind(p->bc[kXlo]) || is_wall_kind(p->bc[kXhi])) return false;
   if ((p->bc[kXlo] == kPeriodic) != (p->bc[kXhi] == kPeriodic)) return false;
   if ((p->bc[kYlo] == kPeriodic) != (p->bc[kYhi] == kPeriodic)) return false;
   return true;
@@ -123,6 +127,9 @@ void fill_kparams(tclbm_ctx *c) {
   k.h_coll = p.h_collision;
   k.h_force = p.h_force;
   k.wall_rho = p.wall_rho;
+  k.visc_mode = p.viscosity_mode;
+  k.mu0_RT0 = p.mu0 / (p.R * p.T0);
+  k.Pr = p.Pr;
   k.R = p.R;
   k.T0 = p.T0;
   k.b = 2.0 / (p.gamma - 1.0);
@@ -429,9 +436,13 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
 
 tclbm_status tclbm_set_bc(tclbm_handle c, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w) {
   if (!c) return TCLBM_E_INVALID;
-  if (side < 0 || side > 3 || kind < 0 || kind > 2) return TCLBM_E_INVALID;
-  if (kind == kWall && side < kYlo) {
+  if (side < 0 || side > 3 || kind < 0 || kind > kWallAdiabatic) return TCLBM_E_INVALID;
+  if (is_wall_kind(kind) && side < kYlo) {
     set_err(c, "WALL is supported on y sides only");
+    return TCLBM_E_INVALID;
+  }
+  if (kind == kWallAdiabatic && c->p.ny < 4) {
+    set_err(c, "an adiabatic wall needs ny >= 4");
     return TCLBM_E_INVALID;
   }
   if (!(std::isfinite(ux_w) && std::isfinite(uy_w) && std::isfinite(T_w)) || (kind == kWall && !(T_w > 0)))

@@ -9,7 +9,10 @@
 namespace tclbm {
 
 enum StoreKind { kF32 = 0, kF16 = 1, kBF16 = 2, kF64 = 3 };
-enum BcKind { kPeriodic = 0, kBounceBack = 1, kWall = 2 };
+enum BcKind { kPeriodic = 0, kBounceBack = 1, kWall = 2, kWallAdiabatic = 3 };
+
+// node walls (imposed velocity; imposed or adiabatic temperature)
+__host__ __device__ inline bool is_wall_kind(int kind) { return kind == kWall || kind == kWallAdiabatic; }
 enum Side { kXlo = 0, kXhi = 1, kYlo = 2, kYhi = 3 };
 
 // Everything a kernel needs, passed by value.  Physical constants are double
@@ -21,6 +24,8 @@ struct KParams {
   int pitch;        // elements per stored row (>= nx)
   long long plane;  // elements per population plane (pitch * ny)
   int thermal, correction, heq_mode, h_coll, h_force, wall_rho;
+  int visc_mode;  // 1: per-node rates from mu = mu0 T/T0 (mu0 here as mu0/(R T0))
+  double mu0_RT0, Pr;
   int bc[4];
   double wall_ux[4], wall_uy[4], wall_T[4];
   double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;

@@ -129,18 +129,19 @@ struct Real<kF64> {
 // stores are then straight-line code without uniform branches in between.
 __host__ __device__ inline bool default_scheme(const KParams &k) {
   return k.thermal == 1 && k.correction == 1 && k.heq_mode == 0 && k.h_coll == 0 && k.h_force == 1 &&
-         k.wall_rho == 0 && k.axf == nullptr;
+         k.wall_rho == 0 && k.axf == nullptr && k.visc_mode == 0;
 }
 
 struct Flags {
   int thermal, wall_rho;
   bool field;  // per-node acceleration
+  bool visc;   // per-node rates from mu = mu0 T/T0
 };
 
 template <int M>
 __device__ __forceinline__ Flags flags(const KParams &k) {
-  if (M == 1) return Flags{1, 0, false};
-  return Flags{k.thermal, k.wall_rho, k.axf != nullptr};
+  if (M == 1) return Flags{1, 0, false, false};
+  return Flags{k.thermal, k.wall_rho, k.axf != nullptr, k.visc_mode == 1};
 }
 
 template <class R, int M = 0>
@@ -389,12 +390,11 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
 template <class R, int M = 0>
 __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const RowRef<R> &qw,
                                           const RowRef<R> &qI, const R *dI, const R *gI, const Macro<R> &mI,
-                                          R axI, R ayI, R axW, R ayW, R *dw, R *gw) {
+                                          R axI, R ayI, R axW, R ayW, R thw, R *dw, R *gw) {
   const R aI_n = (side == kYlo) ? -ayI : ayI;
   const R aW_n = (side == kYlo) ? -ayW : ayW;
   const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
   const Flags fl = flags<M>(k);
-  const R thw = fl.thermal ? c.R_ * (R)k.wall_T[side] : c.R_ * c.T0;
   R drw;
   if (fl.wall_rho == 1) {
     drw = mI.drho + (qI.rho - qw.rho);
@@ -445,7 +445,7 @@ __device__ __forceinline__ void finish(const KParams &k, const Consts<R> &c, int
 }
 
 __device__ __forceinline__ bool is_wall_row(const KParams &k, int y) {
-  return (y == 0 && k.bc[kYlo] == kWall) || (y == k.ny - 1 && k.bc[kYhi] == kWall);
+  return (y == 0 && is_wall_kind(k.bc[kYlo])) || (y == k.ny - 1 && is_wall_kind(k.bc[kYhi]));
 }
 
 // State of row y (not a WALL row): pull and evaluate.
@@ -485,7 +485,15 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   R axI, ayI, axW, ayW;
   node_accel<R, M>(k, yf, col.xc, axI, ayI);
   node_accel<R, M>(k, y, col.xc, axW, ayW);
-  wall_node<R, M>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, s.f, s.h);
+  R thw = c.R_ * (flags<M>(k).thermal ? (R)k.wall_T[side] : c.T0);
+  if (flags<M>(k).thermal && k.bc[side] == kWallAdiabatic) {
+    // zero normal temperature gradient to second order, -3 T_w + 4 T_1 - T_2 = 0,
+    // with the row two inside the wall evaluated here (ny >= 4: a fluid row)
+    RowState<R> two;
+    get_row<S, M>(k, c, (y == 0) ? 2 : y - 2, col, two);
+    thw = (R(4) * in.m.th - two.m.th) * (R(1) / R(3));
+  }
+  wall_node<R, M>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, thw, s.f, s.h);
   finish<R, M>(k, c, y, col.xc, s);
 }
 
@@ -522,7 +530,16 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   R ax, ay;
   node_accel<R, M>(k, y, col.xc, ax, ay);
   R P[9], Q[9];
-  collide<R, (S == kF32 || S == kF64)>(c, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
+  Consts<R> cn = c;
+  if (flags<M>(k).visc) {
+    // mu = mu0 T/T0 in Eq. (29), p = rho R T: 1/w1 = mu0/(rho R T0) + 1/2; w_h and
+    // tau_hf follow from that w1 at constant Pr
+    const R mp = (R)k.mu0_RT0 / s.m.rho;
+    cn.w1 = R(1) / (mp + R(0.5));
+    cn.wh = R(1) / (mp / (R)k.Pr + R(0.5));
+    cn.inv_tau_hf = cn.w1 * ((R)k.Pr - R(1));
+  }
+  collide<R, (S == kF32 || S == kF64)>(cn, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
   if (!store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
   const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("TCLBM_LIB") or os.path.join(_HERE, "_lib", "libtclbm.
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSTABLE = range(6)
 STORE = {"f32": 0, "f16": 1, "bf16": 2, "f64": 3}
-PERIODIC, BOUNCEBACK, WALL = 0, 1, 2
+PERIODIC, BOUNCEBACK, WALL, WALL_ADIABATIC = 0, 1, 2, 3
 XLO, XHI, YLO, YHI = 0, 1, 2, 3
 
 
@@ -36,6 +36,7 @@ class tclbm_params(ctypes.Structure):
         ("h_force", ctypes.c_int32), ("accel_field", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 4),
         ("wall_ux", ctypes.c_double * 4), ("wall_uy", ctypes.c_double * 4), ("wall_T", ctypes.c_double * 4),
+        ("viscosity_mode", ctypes.c_int32), ("mu0", ctypes.c_double),
     ]
 
 
@@ -258,7 +259,8 @@ class Lattice:
         import torch
         self.case = case
         p = tclbm_default_params(case.nx, case.ny)
-        for name in ("R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay", "thermal", "correction"):
+        for name in ("R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay", "thermal", "correction",
+                     "viscosity_mode", "mu0"):
             setattr(p, name, getattr(case, name))
         p.storage = STORE[storage]
         p.accel_field = 1 if case.ax_field is not None else 0

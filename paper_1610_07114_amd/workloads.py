@@ -27,7 +27,7 @@ import numpy as np
 R_LAT = 1.0 / 3.0
 T_REF = 1.0
 
-PERIODIC, BOUNCEBACK, WALL = 0, 1, 2
+PERIODIC, BOUNCEBACK, WALL, WALL_ADIABATIC = 0, 1, 2, 3
 XLO, XHI, YLO, YHI = 0, 1, 2, 3
 
 
@@ -58,6 +58,8 @@ class Case:
     T: Optional[np.ndarray] = None
     ax_field: Optional[np.ndarray] = None
     ay_field: Optional[np.ndarray] = None
+    viscosity_mode: int = 0              # 1: mu = mu0 T/T0 (Section 5B)
+    mu0: float = 0.0
     steps: int = 0                       # nominal run length of the problem
     meta: dict = field(default_factory=dict)
 
@@ -111,6 +113,23 @@ def couette_closed_form(case: Case) -> Tuple[np.ndarray, np.ndarray]:
     u = m["u0"] * eta
     T = m["T_bottom"] + (m["T_top"] - m["T_bottom"]) * eta + case.Pr * m["u0"] ** 2 / (2.0 * cp) * eta * (1 - eta)
     return u, T
+
+
+def couette_variable_viscosity(Pr: float = 5.0, gamma: float = 5.0 / 3.0, Ma: float = 0.35, nx: int = 5,
+                               ny: int = 40, mu0: float = 0.35, w2: float = 1.1, w3: float = 1.6, w4: float = 0.3,
+                               steps: int = 120000) -> Case:
+    """The thermal Couette flow of Section 5B: dynamic viscosity mu = mu0 T/T0
+    (mu0 = 0.35), constant Pr; the upper plate (node wall at y = ny-1) moves at
+    U = Ma sqrt(gamma R T0) with T = T0; the lower plate (y = 0) is fixed and
+    adiabatic; periodic in x; 5 x 40 nodes, w2, w3, w4 = 1.1, 1.6, 0.3.  Starts
+    from rest at T0 and unit density.  tau_f records 1/w1 at unit density."""
+    U = Ma * math.sqrt(gamma * R_LAT * T_REF)
+    return Case(
+        name="couette_mu_T", nx=nx, ny=ny, tau_f=mu0 / (R_LAT * T_REF) + 0.5, w2=w2, w3=w3, w4=w4, gamma=gamma,
+        Pr=Pr, bc=(PERIODIC, PERIODIC, WALL_ADIABATIC, WALL), wall_ux=(0.0, 0.0, 0.0, U),
+        wall_T=(1.0, 1.0, T_REF, T_REF), rho=_full(ny, nx, 1.0), ux=_full(ny, nx, 0.0), uy=_full(ny, nx, 0.0),
+        T=_full(ny, nx, T_REF), viscosity_mode=1, mu0=mu0, steps=steps,
+        meta=dict(U=U, Ma=Ma, H=ny - 1, mu0=mu0))
 
 
 # --------------------------------------------------------------------------------

@@ -30,7 +30,8 @@ def oracle_params(case, **over) -> O.Params:
     kw = dict(nx=case.nx, ny=case.ny, R=case.R, T0=case.T0, gamma=case.gamma, Pr=case.Pr, tau_f=case.tau_f,
               w2=case.w2, w3=case.w3, w4=case.w4, ax=case.ax, ay=case.ay, thermal=case.thermal,
               correction=case.correction, bc=case.bc, wall_ux=case.wall_ux, wall_uy=case.wall_uy,
-              wall_T=case.wall_T, ax_field=case.ax_field, ay_field=case.ay_field)
+              wall_T=case.wall_T, ax_field=case.ax_field, ay_field=case.ay_field,
+              viscosity_mode=case.viscosity_mode, mu0=case.mu0)
     kw.update(over)
     return O.Params(**kw)
 

@@ -37,6 +37,8 @@ def vel_scale(case):
         return m["uc"]
     if case.name in ("couette", "taylor_green"):
         return m["u0"]
+    if case.name == "couette_mu_T":
+        return m["U"]
     if case.name == "shock_tube":
         return float(np.sqrt(case.gamma * case.R * m["T"]))
     return 0.0
@@ -114,6 +116,43 @@ def test_couette_fp32(T):
     e = rel_err(g, o, case)
     say(f"  errors {e}")
     assert max(e.values()) < 1e-5
+
+
+def test_couette_variable_viscosity_fp64_both_orientations(T):
+    """Section 5B's Couette flow (mu = mu0 T/T0, per-node w1, w_h, tau_hf;
+    adiabatic plate), FP64, 20000 steps against the oracle: as printed
+    (adiabatic bottom) and mirrored (adiabatic top, moving bottom plate)."""
+    case = W.couette_variable_viscosity(Pr=5.0, gamma=5.0 / 3.0)
+    U = case.meta["U"]
+    mirrored = case.with_(bc=(W.PERIODIC, W.PERIODIC, W.WALL, W.WALL_ADIABATIC), wall_ux=(0.0, 0.0, U, 0.0))
+    for c, label in ((case, "adiabatic bottom"), (mirrored, "adiabatic top")):
+        say(f"case couette mu(T) 5x40 fp64 20000 steps, {label}")
+        g, o, _ = run_pair(T, c, 20000, storage="f64")
+        e = rel_err(g, o, c)
+        say(f"  errors {e}")
+        assert max(e.values()) < 1e-10
+
+
+def test_couette_variable_viscosity_fp32_table2(T):
+    """FP32 at 100 steps within 1e-5 of the oracle; then the steady bottom-wall
+    temperature of all four Table 2 cases (Section 5B) within 1e-5 of the
+    oracle's steady value and within 1.5% of the analytical rise."""
+    case = W.couette_variable_viscosity(Pr=4.0, gamma=1.5)
+    say("case couette mu(T) 5x40 fp32 100 steps")
+    g, o, _ = run_pair(T, case, 100)
+    e = rel_err(g, o, case)
+    say(f"  errors {e}")
+    assert max(e.values()) < 1e-5
+    O.set_num_threads(4)
+    for Pr, gam in ((5.0, 5.0 / 3.0), (5.0, 1.5), (4.0, 5.0 / 3.0), (4.0, 1.5)):
+        c = W.couette_variable_viscosity(Pr=Pr, gamma=gam)
+        say(f"case couette mu(T) Pr {Pr} gamma {gam:.4f} fp32 60000 steps")
+        g, o, _ = run_pair(T, c, 60000)
+        A = Pr * (gam - 1.0) / 2.0 * 0.35 ** 2
+        tb, tb_o = float(g[3][0, 0]), float(o[3][0, 0])
+        say(f"  bottom T {tb:.6f} oracle {tb_o:.6f} analytical {1 + A:.6f}")
+        assert abs(tb - tb_o) < 1e-5
+        assert abs((tb - 1.0) / A - 1.0) < 0.015
 
 
 def test_rb_fp32_100_steps(T):

@@ -57,7 +57,8 @@ def test_state_bytes_plan(T):
 @pytest.mark.parametrize("field,value", [("nx", 2), ("ny", 0), ("tau_f", 0.5), ("gamma", 1.0), ("Pr", 0.0),
                                          ("w2", 2.0), ("w3", 0.0), ("storage", 7), ("R", 0.5),
                                          ("wall_rho", 3), ("h_collision", 2), ("h_force", 2), ("thermal", 2),
-                                         ("bc", (2, 2, 0, 0)), ("bc", (1, 0, 0, 0)), ("bc", (0, 0, 2, 0))])
+                                         ("bc", (2, 2, 0, 0)), ("bc", (1, 0, 0, 0)), ("bc", (0, 0, 2, 0)),
+                                         ("bc", (3, 3, 0, 0)), ("bc", (0, 0, 4, 4)), ("viscosity_mode", 2)])
 def test_invalid_parameters_rejected(T, field, value):
     p = T.tclbm_default_params(16, 16)
     if field == "bc":
@@ -73,6 +74,21 @@ def test_invalid_parameters_rejected(T, field, value):
     st = T._lib.tclbm_create(ctypes.byref(p), ctypes.c_void_p(1 << 20), 1 << 30, None, T._dp(o), T._dp(z),
                              T._dp(z), T._dp(o), None, None, ctypes.byref(h))
     assert st == T.E_INVALID and not h.value
+
+
+def test_viscosity_law_and_adiabatic_wall_validation(T):
+    """mu = mu0 T/T0 needs mu0 > 0; an adiabatic wall needs ny >= 4 (its
+    temperature uses the two rows inside) and a y side."""
+    p = T.tclbm_default_params(16, 16)
+    p.viscosity_mode = 1
+    assert T.tclbm_state_bytes(p) == 0
+    p.mu0 = 0.35
+    assert T.tclbm_state_bytes(p) > 0
+    q = T.tclbm_default_params(5, 3)
+    q.bc[2], q.bc[3] = T.WALL_ADIABATIC, T.WALL
+    assert T.tclbm_state_bytes(q) == 0
+    q.ny = 4
+    assert T.tclbm_state_bytes(q) > 0
 
 
 def test_small_buffer_and_bad_fields_rejected(T):
