@@ -554,7 +554,10 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 }  // namespace
 
 // ------------------------------------------------------------ step kernel ---
-constexpr int kStepWaves = 4;
+#ifndef TCLBM_STEP_WAVES
+#define TCLBM_STEP_WAVES 4
+#endif
+constexpr int kStepWaves = TCLBM_STEP_WAVES;  // waves per block
 
 // Build-time launch shape of the step kernels (defaults chosen by measurement).
 

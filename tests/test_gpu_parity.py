@@ -258,12 +258,15 @@ def test_instability_is_reported(T):
 
 
 def test_batch_equals_members_alone_bitwise(T):
-    """A batch of uneven lattices (walls, bounce-back, periodic; one launch per
-    step) gives exactly the states of the same lattices stepped alone."""
+    """A batch of uneven lattices (walls, bounce-back, periodic, an adiabatic
+    wall with per-node rates; one launch per step, members of both kernel
+    instantiations) gives exactly the states of the same lattices stepped
+    alone."""
     import torch
     cases = [W.rayleigh_benard(nx=130, ny=67, seed=1, noise=1e-3), W.couette(),
-             W.shock_tube(nx=700, ny=5), W.uniform_noise(64, 40, seed=2, ax=1e-5)]
-    say("case batch of 4 uneven lattices fp32, 75 steps, vs alone")
+             W.shock_tube(nx=700, ny=5), W.uniform_noise(64, 40, seed=2, ax=1e-5),
+             W.couette_variable_viscosity(Pr=4.0, gamma=1.5)]
+    say("case batch of 5 uneven lattices fp32, 75 steps, vs alone")
     stream = torch.cuda.Stream()
     alone, together = [], []
     for cs in cases:
