@@ -158,9 +158,12 @@ void decompose(tclbm_ctx *c) {
   int rows = c->strip_rows_req;
   if (rows <= 0) {
     // enough waves to fill 256 CUs many times over: strips of a few rows when
-    // the lattice is large (halo rows are re-pulled once per strip, mostly
-    // from L2), down to a single row when it is small
-    const long long target = 65536;
+    // the lattice is large, down to a single row when it is small.  Halo rows
+    // are re-pulled once per strip, yet on 8192x4096 shorter strips measured
+    // faster for FP32 (4 rows: 1204 us, 8: 1237, 33: 1414) while the 16-bit
+    // kernels prefer longer ones (FP16 4 rows: 919 us, 8: 839, 12: 816).
+    const int st = c->p.storage;
+    const long long target = (st == kF32) ? 131072 : (st == kF64 ? 65536 : 32768);
     long long r = ((long long)k.ny * k.n_xtiles) / target;
     rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }
