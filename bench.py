@@ -21,6 +21,8 @@ line also carries, measured in the same run:
                   with continuous batching and 16-bit storage (solves/s,
                   p50/p99 latency, Nu error against stored FP64 values), and the
                   same stream through the plain one-lattice-at-a-time FP32 path
+  hbm_ceiling     a plain chunked 2 GiB copy on the same GPU; roofline_large
+                  and batch also state their fraction of it
 """
 from __future__ import annotations
 
@@ -112,7 +114,8 @@ def cpu_baseline(cases, seconds_target: float = 12.0, label=None):
 # ------------------------------------------------------------------- probes ---
 def copy_probe(torch, tclbm, nbytes: int = 2 << 30, reps: int = 20):
     """Achievable HBM bandwidth of a plain streaming copy (read + write bytes per
-    launch / launch time), the measured ceiling beside the 8 TB/s peak."""
+    launch / launch time; each block copies one contiguous 16 KiB chunk), the
+    measured ceiling beside the 8 TB/s peak."""
     dev = torch.device("cuda:0")
     s = torch.cuda.Stream(dev)
     with torch.cuda.stream(s):
@@ -392,6 +395,12 @@ def main():
         del big
         log("bench: batched RB, 256 instances, f32")
         out["batch"] = bench_batch(torch, tclbm, storage="f32")
+        # the measured ceiling beside the specification: a plain chunked copy
+        log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
+        ceil = copy_probe(torch, tclbm)
+        out["hbm_ceiling"] = ceil
+        out["roofline_large"]["frac_of_ceiling"] = round(out["roofline_large"]["achieved"] / ceil["GBs"], 4)
+        out["batch"]["roofline"]["frac_of_ceiling"] = round(out["batch"]["roofline"]["achieved"] / ceil["GBs"], 4)
         log(f"bench: serving stream, {args.requests} requests, {args.serve_storage}")
         out["serving"] = bench_serving(torch, tclbm, n_requests=args.requests, storage=args.serve_storage)
 

@@ -1049,26 +1049,30 @@ hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipSt
 // -------------------------------------------------------- HBM copy probe ---
 // Plain streaming copy (16-byte vectors, grid-stride) used to measure the
 // achievable HBM bandwidth and to calibrate byte counters.
+// Each block copies one contiguous chunk of 1024 16-byte words (16 KiB): four
+// coalesced 16-byte loads per thread in flight, then the four stores.
+constexpr int kCopyChunk = 1024;
+
 __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                                    long long n16) {
-  // four independent 16-byte loads in flight per thread
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+  const long long i = (long long)blockIdx.x * kCopyChunk + threadIdx.x;
+  if (i + 3 * 256 < n16) {
+    const uint4 a = src[i], b = src[i + 256], c = src[i + 512], d = src[i + 768];
     dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
+    dst[i + 256] = b;
+    dst[i + 512] = c;
+    dst[i + 768] = d;
+    return;
   }
-  for (; i < n16; i += stride) dst[i] = src[i];
+  for (int q = 0; q < 4; ++q)
+    if (i + q * 256 < n16) dst[i + q * 256] = src[i + q * 256];
 }
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
   const long long n16 = (long long)(bytes / 16);
   if (n16 <= 0) return hipSuccess;
-  long long blocks = (n16 + 4 * 256 - 1) / (4 * 256);
-  if (blocks > 256 * 32) blocks = 256 * 32;
+  const long long blocks = (n16 + kCopyChunk - 1) / kCopyChunk;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const uint4 *>(src),
                      reinterpret_cast<uint4 *>(dst), n16);
   return hipGetLastError();
