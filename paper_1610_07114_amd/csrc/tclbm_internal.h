@@ -43,6 +43,15 @@ struct KParams {
   int par;
 };
 
+// The default thermal scheme (the step kernels have a compile-time
+// instantiation of it): correction on, continuous h^eq moments, two-rate
+// energy update with its force source, wall density from the known
+// populations, uniform acceleration, constant w1.
+__host__ __device__ inline bool default_scheme(const KParams &k) {
+  return k.thermal == 1 && k.correction == 1 && k.heq_mode == 0 && k.h_coll == 0 && k.h_force == 1 &&
+         k.wall_rho == 0 && k.axf == nullptr && k.visc_mode == 0;
+}
+
 // Reduction record written per block by the moments kernel.
 enum { kSumMass = 0, kSumMx, kSumMy, kSumE, kSumKin, kSumNu, kSumRhoMin, kSumTMin, kSumBad, kNumSums };
 
@@ -52,7 +61,7 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
 int step_waves_per_block();
 // one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
-                             int storage, int parity, hipStream_t s);
+                             int storage, int parity, bool all_default, hipStream_t s);
 hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
                        const double *d_uy, const double *d_T, hipStream_t s);
 // fields (device, double, nx*ny each, nullable) and per-block partial sums

@@ -127,10 +127,6 @@ struct Real<kF64> {
 // moments, the two-rate energy update with its force source, the wall density
 // from the known populations, uniform acceleration): its pulls, collision and
 // stores are then straight-line code without uniform branches in between.
-__host__ __device__ inline bool default_scheme(const KParams &k) {
-  return k.thermal == 1 && k.correction == 1 && k.heq_mode == 0 && k.h_coll == 0 && k.h_force == 1 &&
-         k.wall_rho == 0 && k.axf == nullptr && k.visc_mode == 0;
-}
 
 struct Flags {
   int thermal, wall_rho;
@@ -554,15 +550,32 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 }  // namespace
 
 // ------------------------------------------------------------ step kernel ---
+// Build-time switches of the step kernels (defaults chosen by measurement on
+// MI355X; the others exist for A/B comparisons):
+//   TCLBM_STEP_WAVES          waves per block (4)
+//   TCLBM_LDS_PULL            FP32 rows pulled one row ahead into LDS (1)
+//   TCLBM_SCHEME_SPECIAL      compile-time instantiation of the default scheme (1)
+//   TCLBM_F32_WAVES_PER_EU    occupancy cap of the FP32 step kernel (0: none)
+//   TCLBM_WAVES_PER_EU        occupancy cap of the 16-bit step kernels (3)
+//   TCLBM_BATCH_WAVES_PER_EU  occupancy cap of the FP32/16-bit batch kernels (3)
 #ifndef TCLBM_STEP_WAVES
 #define TCLBM_STEP_WAVES 4
 #endif
-constexpr int kStepWaves = TCLBM_STEP_WAVES;  // waves per block
-
-// Build-time launch shape of the step kernels (defaults chosen by measurement).
+constexpr int kStepWaves = TCLBM_STEP_WAVES;
 
 #ifndef TCLBM_LDS_PULL
 #define TCLBM_LDS_PULL 1
+#endif
+#ifndef TCLBM_SCHEME_SPECIAL
+#define TCLBM_SCHEME_SPECIAL 1
+#endif
+#ifndef TCLBM_F32_WAVES_PER_EU
+#define TCLBM_F32_WAVES_PER_EU 0
+#endif
+#if TCLBM_F32_WAVES_PER_EU > 0
+#define TCLBM_F32_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_F32_WAVES_PER_EU, TCLBM_F32_WAVES_PER_EU)))
+#else
+#define TCLBM_F32_OCC
 #endif
 #ifndef TCLBM_WAVES_PER_EU
 #define TCLBM_WAVES_PER_EU 3
@@ -571,6 +584,14 @@ constexpr int kStepWaves = TCLBM_STEP_WAVES;  // waves per block
 #define TCLBM_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_WAVES_PER_EU, TCLBM_WAVES_PER_EU)))
 #else
 #define TCLBM_OCC
+#endif
+#ifndef TCLBM_BATCH_WAVES_PER_EU
+#define TCLBM_BATCH_WAVES_PER_EU 3
+#endif
+#if TCLBM_BATCH_WAVES_PER_EU > 0
+#define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
+#else
+#define TCLBM_BATCH_OCC
 #endif
 
 // The march of one wave over its (x tile, strip) of lattice k.
@@ -702,18 +723,6 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
   }
 }
 
-#ifndef TCLBM_SCHEME_SPECIAL
-#define TCLBM_SCHEME_SPECIAL 1
-#endif
-#ifndef TCLBM_F32_WAVES_PER_EU
-#define TCLBM_F32_WAVES_PER_EU 0
-#endif
-#if TCLBM_F32_WAVES_PER_EU > 0
-#define TCLBM_F32_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_F32_WAVES_PER_EU, TCLBM_F32_WAVES_PER_EU)))
-#else
-#define TCLBM_F32_OCC
-#endif
-
 template <int S, int M>
 __global__ __launch_bounds__(64 * kStepWaves) TCLBM_F32_OCC void step_kernel(KParams k) {
   // wave-uniform: rows, strips and table reads stay scalar
@@ -741,16 +750,10 @@ __global__ __launch_bounds__(64 * kStepWaves) void step_kernel_f64(KParams k) {
 // wave_start[i] is the first global wave of instance i (prefix sum of
 // n_xtiles * n_strips, wave_start[n] = total); waves of one instance are
 // contiguous, in table order (largest lattices first).
-#ifndef TCLBM_BATCH_WAVES_PER_EU
-#define TCLBM_BATCH_WAVES_PER_EU 3
-#endif
-#if TCLBM_BATCH_WAVES_PER_EU > 0
-#define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
-#else
-#define TCLBM_BATCH_OCC
-#endif
 
-template <int S>
+// MB = 1: every member runs the default scheme (the host checked), so only
+// that instantiation is compiled in; MB = 0: chosen per member.
+template <int S, int MB>
 __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, const int *__restrict__ wave_start,
                                            int n_inst, int parity) {
   const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
@@ -771,34 +774,46 @@ __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, cons
     __shared__ float buf[kStepWaves * 2 * kLdsSlot];
     lds = (LdsF *)(buf + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 2 * kLdsSlot);
   }
-  if (TCLBM_SCHEME_SPECIAL && default_scheme(k)) march<S, 1>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
-  else march<S, 0>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+  if constexpr (MB == 1) {
+    march<S, 1>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+  } else {
+    if (TCLBM_SCHEME_SPECIAL && default_scheme(k)) march<S, 1>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+    else march<S, 0>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+  }
 }
 
 // 32- and 16-bit storage may take a register cap (occupancy); FP64 never does
-template <int S>
+template <int S, int MB>
 __global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH_OCC void batch_step_kernel(
     const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity) {
-  batch_body<S>(tab, wave_start, n_inst, parity);
+  batch_body<S, MB>(tab, wave_start, n_inst, parity);
 }
+template <int MB>
 __global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel_f64(const KParams *__restrict__ tab,
                                                                          const int *__restrict__ wave_start,
                                                                          int n_inst, int parity) {
-  batch_body<kF64>(tab, wave_start, n_inst, parity);
+  batch_body<kF64, MB>(tab, wave_start, n_inst, parity);
 }
 
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
-                             int storage, int parity, hipStream_t s) {
+                             int storage, int parity, bool all_default, hipStream_t s) {
   if (total_waves <= 0) return hipSuccess;
   const int blocks = (total_waves + kStepWaves - 1) / kStepWaves;
   dim3 grid(blocks), block(64 * kStepWaves);
+  const bool d = TCLBM_SCHEME_SPECIAL && all_default;
+#define TCLBM_BATCH_LAUNCH(K0, K1)                                                  \
+  do {                                                                              \
+    if (d) hipLaunchKernelGGL(K1, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); \
+    else hipLaunchKernelGGL(K0, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity);   \
+  } while (0)
   switch (storage) {
-    case kF32: hipLaunchKernelGGL(batch_step_kernel<kF32>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
-    case kF16: hipLaunchKernelGGL(batch_step_kernel<kF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
-    case kBF16: hipLaunchKernelGGL(batch_step_kernel<kBF16>, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
-    case kF64: hipLaunchKernelGGL(batch_step_kernel_f64, grid, block, 0, s, d_tab, d_wave_start, n_inst, parity); break;
+    case kF32: TCLBM_BATCH_LAUNCH((batch_step_kernel<kF32, 0>), (batch_step_kernel<kF32, 1>)); break;
+    case kF16: TCLBM_BATCH_LAUNCH((batch_step_kernel<kF16, 0>), (batch_step_kernel<kF16, 1>)); break;
+    case kBF16: TCLBM_BATCH_LAUNCH((batch_step_kernel<kBF16, 0>), (batch_step_kernel<kBF16, 1>)); break;
+    case kF64: TCLBM_BATCH_LAUNCH((batch_step_kernel_f64<0>), (batch_step_kernel_f64<1>)); break;
     default: return hipErrorInvalidValue;
   }
+#undef TCLBM_BATCH_LAUNCH
   return hipGetLastError();
 }
 
