@@ -170,12 +170,14 @@ def bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, strip
 
 
 # -------------------------------------------------------------------- batch ---
-def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, autotune=True):
+def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, strip_rows=0, graph_chunk=None,
+                traffic_json=None):
     """The batched workload: n seeded 2N x N Rayleigh-Benard lattices (N
     log-uniform on [32, 512], Ra log-uniform on [1e4, 1e6], Pr uniform on
     [0.5, 7]) advanced together, one launch per step, HIP-graph chunks.  The
     autotuner's trial steps (strip height x graph chunk) are part of the
-    warm-up."""
+    warm-up; a given strip height (and graph chunk) replaces the autotuner.
+    `traffic` is the stored counter measurement for the strip height in use."""
     from paper_1610_07114_amd import serving as S
     from paper_1610_07114_amd import workloads as W
     specs = W.batched_rb_specs(n, seed=seed)
@@ -188,9 +190,14 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
     log(f"batch: {n} seeded lattices resident ({time.perf_counter() - t0:.1f} s)")
     b = tclbm.Batch(lats)
     tune = None
-    if autotune:
+    if strip_rows > 0:
+        b.set_strip_rows(strip_rows)
+        if graph_chunk is not None:
+            b.set_graph_chunk(graph_chunk)
+    else:
         tune = S.autotune_batch(b, log=log)
         log(f"batch autotune: {tune}")
+    rows_in_use = b.strip_rows
     b.step(warmup)
     stream.synchronize()
     t0 = time.perf_counter()
@@ -209,7 +216,10 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
             "instances": n, "nodes": nodes, "storage": storage, "steps": steps, "warmup": warmup,
             "mlups": round(nodes * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
             "autotune": tune, "waves_per_step": waves, "unstable_instances": int(unstable),
-            "roofline": roofline(bpl, nodes, avg, kernel="batch_step_kernel")}
+            "strip_rows": rows_in_use,
+            "roofline": roofline(bpl, nodes, avg,
+                                 load_traffic(traffic_json, f"batched_rayleigh_benard_{n}_{storage}_rows{rows_in_use}")
+                                 if traffic_json else None, kernel="batch_step_kernel")}
 
 
 # ------------------------------------------------------------------ serving ---
@@ -304,6 +314,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--reduce-every", type=int, default=1000)
     ap.add_argument("--strip-rows", type=int, default=0)
+    ap.add_argument("--batch-strip-rows", type=int, default=0,
+                    help="batch workload: fixed strip height (with --graph-chunk) instead of the autotuner")
     ap.add_argument("--graph-chunk", type=int, default=32)
     ap.add_argument("--requests", type=int, default=500, help="serving stream length")
     ap.add_argument("--serve-storage", default="f16", choices=["f16", "bf16", "f32"])
@@ -331,7 +343,9 @@ def main():
     if args.workload == "batch":
         log("bench: batched RB workload, 256 instances")
         b = bench_batch(torch, tclbm, storage=args.storage, steps=min(args.steps, 2000),
-                        warmup=min(args.warmup, 400))
+                        warmup=min(args.warmup, 400), strip_rows=args.batch_strip_rows,
+                        graph_chunk=args.graph_chunk if args.batch_strip_rows > 0 else None,
+                        traffic_json=args.traffic_json)
         out = {"metric": "TCLBM MLUPS", "value": b["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": b["steps"],
                "warmup": b["warmup"], "ms_per_step": b["ms_per_step"], "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
@@ -394,7 +408,7 @@ def main():
                                             load_traffic(args.traffic_json, f"{bname}_f32"))}
         del big
         log("bench: batched RB, 256 instances, f32")
-        out["batch"] = bench_batch(torch, tclbm, storage="f32")
+        out["batch"] = bench_batch(torch, tclbm, storage="f32", traffic_json=args.traffic_json)
         # the measured ceiling beside the specification: a plain chunked copy
         log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
         ceil = copy_probe(torch, tclbm)
