@@ -629,6 +629,7 @@ struct tclbm_batch {
   int strip_rows_req;  // batch strip height (0: automatic), overrides the members'
   int strip_rows;      // the height in use
   bool all_default;    // every member runs the default scheme (leaner kernel)
+  bool all_fit;        // every member's state buffers allow buffer addressing
   char err[256];
 };
 
@@ -650,9 +651,11 @@ static hipError_t batch_upload(tclbm_batch *b) {
   std::vector<KParams> tab(2 * n);  // [0, n): even steps; [n, 2n): odd steps (src, dst swapped)
   std::vector<int> start(n + 1, 0);
   b->all_default = true;
+  b->all_fit = true;
   for (int i = 0; i < n; ++i) {
     tclbm_handle h = b->m[i];
     b->all_default = b->all_default && default_scheme(h->k);
+    b->all_fit = b->all_fit && buffer_fits(h->k, b->storage);
     tab[i] = h->k;
     tab[i].src = h->buf[h->cur];
     tab[i].dst = h->buf[1 - h->cur];
@@ -681,7 +684,7 @@ static void batch_drop_graph(tclbm_batch *b) {
 static tclbm_status batch_launch(tclbm_batch *b, int64_t n) {
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, b->parity,
-                                     b->all_default, b->stream);
+                                     b->all_default, b->all_fit, b->stream);
     if (e != hipSuccess) {
       snprintf(b->err, sizeof(b->err), "batch launch: %s", hipGetErrorString(e));
       return TCLBM_E_DEVICE;
@@ -763,7 +766,7 @@ tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
       hipError_t le = hipSuccess;
       for (int s = 0; s < ch && le == hipSuccess && e == hipSuccess; ++s)
         le = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, s & 1,
-                               b->all_default, b->stream);
+                               b->all_default, b->all_fit, b->stream);
       hipError_t ee = (e == hipSuccess) ? hipStreamEndCapture(b->stream, &g) : e;
       if (e != hipSuccess || le != hipSuccess || ee != hipSuccess) {
         if (e == hipSuccess && ee == hipSuccess) hipGraphDestroy(g);

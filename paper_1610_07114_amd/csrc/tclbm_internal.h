@@ -52,6 +52,13 @@ __host__ __device__ inline bool default_scheme(const KParams &k) {
          k.wall_rho == 0 && k.axf == nullptr && k.visc_mode == 0;
 }
 
+// Buffer-resource addressing of the default scheme (16-bit storage): one
+// descriptor per state buffer, so its 18 planes must span less than 4 GiB.
+__host__ __device__ inline bool buffer_fits(const KParams &k, int storage) {
+  if (storage != kF16 && storage != kBF16) return false;
+  return 18ull * (unsigned long long)k.plane * 2ull < (1ull << 32);
+}
+
 // Reduction record written per block by the moments kernel.
 enum { kSumMass = 0, kSumMx, kSumMy, kSumE, kSumKin, kSumNu, kSumRhoMin, kSumTMin, kSumBad, kNumSums };
 
@@ -61,7 +68,7 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
 int step_waves_per_block();
 // one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
-                             int storage, int parity, bool all_default, hipStream_t s);
+                             int storage, int parity, bool all_default, bool all_fit, hipStream_t s);
 hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
                        const double *d_uy, const double *d_T, hipStream_t s);
 // fields (device, double, nx*ny each, nullable) and per-block partial sums

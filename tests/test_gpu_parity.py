@@ -230,6 +230,19 @@ def test_16bit_storage_parity(T, storage, tol):
     assert max(e["rho"], e["T"]) < tol
 
 
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_16bit_storage_bounce_back_ends(T, storage, tol):
+    """16-bit storage on a lattice whose x ends bounce back (the per-lane
+    opposite-plane reads of the buffer-addressed pull) and whose y sides are
+    walls: the shock tube, 100 steps, against the oracle."""
+    case = W.shock_tube(nx=300, ny=6).with_(bc=(W.BOUNCEBACK, W.BOUNCEBACK, W.WALL, W.WALL))
+    say(f"case shock tube 300x6 walled {storage} storage 100 steps")
+    g, o, _ = run_pair(T, case, 100, storage=storage)
+    e = rel_err(g, o, case)
+    say(f"  errors {e}")
+    assert max(e.values()) < tol
+
+
 def test_conservation_sums_fp64(T):
     case = W.uniform_noise(96, 50, seed=9, ax=2e-5, ay=1e-5)
     say("case periodic conservation fp64 96x50")
