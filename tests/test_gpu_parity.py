@@ -371,6 +371,24 @@ def test_full_size_rb_8192x4096_vs_oracle(T):
     assert max(e.values()) < 1e-5
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_full_size_rb_8192x4096_16bit_vs_oracle(T, storage, tol):
+    """The same full-size lattice with 16-bit storage (buffer-addressed kernel,
+    automatic strip height): every node against the FP64 oracle after 10
+    steps, within the 16-bit bounds."""
+    case = W.rayleigh_benard(nx=8192, ny=4096, Ra=1e5, Pr=0.71, seed=0)
+    say(f"case rayleigh-benard 8192x4096 {storage} 10 steps vs oracle")
+    lat = T.Lattice(case, storage=storage)
+    lat.step(10)
+    g = lat.moments()[:4]
+    lat.close()
+    o = oracle_lattice(case).step(10).macros()
+    e = rel_err(g, o, case)
+    say(f"  errors {e}")
+    assert max(e["rho"], e["T"]) < tol
+
+
 def test_full_batch_256_sampled_vs_alone_and_oracle(T):
     """The batched workload as bench.py runs it (256 seeded lattices, one
     launch per step, automatic strip height, graph chunks of 32): a seeded
