@@ -159,11 +159,12 @@ void decompose(tclbm_ctx *c) {
   if (rows <= 0) {
     // enough waves to fill 256 CUs many times over: strips of a few rows when
     // the lattice is large, down to a single row when it is small.  Halo rows
-    // are re-pulled once per strip, yet on 8192x4096 shorter strips measured
-    // faster for FP32 (4 rows: 1204 us, 8: 1237, 33: 1414) while the 16-bit
-    // kernels prefer longer ones (FP16 4 rows: 919 us, 8: 839, 12: 816).
+    // are re-pulled once per strip, yet on 8192x4096 short strips measured
+    // fastest for FP32 (2 rows: 1252 us, 3: 1180, 4: 1204, 8: 1237, 33: 1414)
+    // while the 16-bit kernels prefer longer ones (FP16 4 rows: 919 us, 8: 839,
+    // 12: 816).
     const int st = c->p.storage;
-    const long long target = (st == kF32) ? 131072 : (st == kF64 ? 65536 : 32768);
+    const long long target = (st == kF32) ? 163840 : (st == kF64 ? 65536 : 32768);
     long long r = ((long long)k.ny * k.n_xtiles) / target;
     rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }

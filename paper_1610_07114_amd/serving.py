@@ -240,7 +240,7 @@ def summarize(results: Sequence[Result], wall: float) -> dict:
 
 
 # ----------------------------------------------------------------- autotuner ---
-def autotune_batch(batch, rows=(0, 4, 8, 16, 32), chunks=(8, 16, 32), steps: int = 40, log=None) -> dict:
+def autotune_batch(batch, rows=(0, 2, 4, 8, 16, 32), chunks=(8, 16, 32), steps: int = 40, log=None) -> dict:
     """Time `batch` with every strip height (rows per wave strip, 0 = the
     batch's automatic choice) and HIP-graph chunk, keep the fastest on the
     batch and return it.  Advances the members by
