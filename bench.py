@@ -165,8 +165,9 @@ def bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, strip
     # on the library's stream (graph replays of the same kernel)
     kern_ms = lat.step_timed(steps)
     _, _, _, _, sums = lat.moments(fields=False)
+    kernel = lat.kernel
     lat.close()
-    return dict(wall=wall, dev_ms=dev_ms, avg_launch_s=kern_ms / 1e3 / steps, nodes=nodes, sums=sums)
+    return dict(wall=wall, dev_ms=dev_ms, avg_launch_s=kern_ms / 1e3 / steps, nodes=nodes, sums=sums, kernel=kernel)
 
 
 # -------------------------------------------------------------------- batch ---
@@ -392,7 +393,7 @@ def main():
         "config": {"workload": wname, "nx": case.nx, "ny": case.ny, "storage": args.storage,
                    "steps_per_reduction": args.reduce_every, "device_ms": round(r["dev_ms"], 3)},
         "roofline": roofline(bpl, r["nodes"], r["avg_launch_s"],
-                             load_traffic(args.traffic_json, f"{wname}_{args.storage}")),
+                             load_traffic(args.traffic_json, f"{wname}_{args.storage}"), kernel=r["kernel"]),
         "nu": None,
     }
     if case.name == "rayleigh_benard":
@@ -405,7 +406,7 @@ def main():
         rl = bench_single(torch, tclbm, big, "f32", 1000, 200, 1000, 0, 32)
         out["roofline_large"] = {"workload": bname, "mlups": round(rl["nodes"] * 1000 / rl["wall"] / 1e6, 1),
                                  **roofline(144, rl["nodes"], rl["avg_launch_s"],
-                                            load_traffic(args.traffic_json, f"{bname}_f32"))}
+                                            load_traffic(args.traffic_json, f"{bname}_f32"), kernel=rl["kernel"])}
         del big
         log("bench: batched RB, 256 instances, f32")
         out["batch"] = bench_batch(torch, tclbm, storage="f32", traffic_json=args.traffic_json)

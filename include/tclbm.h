@@ -186,6 +186,13 @@ tclbm_status tclbm_read_state(tclbm_handle h, double *out);
  * depend on either (every node runs the same arithmetic). */
 tclbm_status tclbm_set_tuning(tclbm_handle h, int32_t strip_rows, int32_t graph_chunk);
 
+/* Name of the kernel that one step of this lattice launches under its current
+ * launch shape: "row_group_kernel" (FP32 storage, default scheme, single-row
+ * strips), "step_kernel" (other FP32), "step_kernel_16" (FP16/BF16) or
+ * "step_kernel_f64".  A static string owned by the library; NULL for a NULL
+ * handle.  For profilers and reports: it matches the kernel-trace name. */
+const char *tclbm_step_kernel(tclbm_handle h);
+
 /* Release the handle (waits for its stream).  dev_buf is not freed. */
 tclbm_status tclbm_destroy(tclbm_handle h);
 

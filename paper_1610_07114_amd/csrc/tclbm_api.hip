@@ -558,6 +558,8 @@ tclbm_status tclbm_moments(tclbm_handle c, double *rho, double *ux, double *uy, 
 
 int64_t tclbm_steps_done(tclbm_handle c) { return c ? c->steps : -1; }
 
+const char *tclbm_step_kernel(tclbm_handle c) { return c ? step_kernel_name(c->k, c->p.storage) : nullptr; }
+
 tclbm_status tclbm_read_state(tclbm_handle c, double *out) {
   if (!c || !out) return TCLBM_E_INVALID;
   const size_t cnt = (size_t)c->p.nx * c->p.ny * (c->p.thermal ? 18 : 9);

@@ -65,6 +65,7 @@ enum { kSumMass = 0, kSumMx, kSumMy, kSumE, kSumKin, kSumNu, kSumRhoMin, kSumTMi
 size_t store_bytes(int storage);
 
 hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
+const char *step_kernel_name(const KParams &k, int storage);
 int step_waves_per_block();
 // one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,

@@ -639,6 +639,9 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 //   TCLBM_F32_WAVES_PER_EU    occupancy cap of the FP32 step kernel (0: none)
 //   TCLBM_WAVES_PER_EU        occupancy cap of the 16-bit step kernels (3)
 //   TCLBM_BATCH_WAVES_PER_EU  occupancy cap of the FP32/16-bit batch kernels (3)
+//   TCLBM_ROW_GROUP           rows per block for FP32 lattices of single-row
+//                             strips, neighbours' u_y(1 - theta) shared in LDS
+//                             (4; 1: one independent wave per row)
 #ifndef TCLBM_STEP_WAVES
 #define TCLBM_STEP_WAVES 4
 #endif
@@ -672,6 +675,10 @@ constexpr int kStepWaves = TCLBM_STEP_WAVES;
 #ifndef TCLBM_BATCH_WAVES_PER_EU
 #define TCLBM_BATCH_WAVES_PER_EU 3
 #endif
+#ifndef TCLBM_ROW_GROUP
+#define TCLBM_ROW_GROUP 4
+#endif
+constexpr int kRowGroup = TCLBM_ROW_GROUP;
 #if TCLBM_BATCH_WAVES_PER_EU > 0
 #define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
 #else
@@ -817,6 +824,64 @@ __global__ __launch_bounds__(64 * W) TCLBM_F32_OCC void step_kernel(KParams k) {
   __shared__ float lds[W * 2 * kLdsSlot];
   march<S, M>(k, wave, threadIdx.x & 63, (LdsF *)(lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 2 * kLdsSlot));
 }
+// Lattices of single-row strips, G consecutive rows of one tile column per
+// block, one wave per row.  A row's collision needs u_y(1 - theta) of the rows
+// above and below it (central difference), so a lone wave pulls three rows to
+// collide one.  In a group every wave pulls and finishes its own row, the first
+// and last wave also the row just outside the group, and the waves read their
+// neighbours' values from LDS: (G + 2) / G pulls per collided row instead of 3.
+// The arithmetic per node is that of the lone-wave path, value for value.
+// Groups that touch a non-periodic wall (the one-sided differences and wall
+// rows of the general march) or overhang the lattice run every row as a lone
+// wave.  The condition is the same for the whole block, so either all G waves
+// meet the barrier or none does.
+template <int S, int M, int G>
+__device__ __forceinline__ void row_group(const KParams &k, int grp, int xt, int w, int lane,
+                                          LdsF *qy_share, LdsF *lds) {
+  static_assert(S == kF32, "row groups serve FP32 storage");
+  using R = typename Real<S>::T;
+  const int ny = k.ny;
+  const int g0 = grp * G, y = g0 + w;
+  const bool yper = (k.bc[kYlo] == kPeriodic);
+  if (!(g0 + G <= ny && (yper || (g0 >= 3 && g0 + G <= ny - 3)))) {
+    if (y < ny) march<S, M>(k, y * k.n_xtiles + xt, lane, lds);  // strip y of one row
+    return;
+  }
+  const int xl = xt * k.tile_w - k.lane_off + lane;
+  const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
+  const Col col = make_col(k, xl);
+  const Consts<R> c = make_consts<R, M>(k);
+  const bool edge = (w == 0) || (w == G - 1);  // wave-uniform
+  const int ye = (w == 0) ? (y == 0 ? ny - 1 : y - 1) : (y == ny - 1 ? 0 : y + 1);
+  RowState<R> cur, out;
+  pull_issue<S, M>(k, y, col, cur.f, cur.h);
+  if (edge) pull_issue<S, M>(k, ye, col, out.f, out.h);
+  cur.q = row_ref(k, c, y);
+  pull_shift<S, M>(k, y, col, cur.f, cur.h);
+  finish<R, M>(k, c, y, col.xc, cur);
+  qy_share[(w + 1) * 64 + lane] = cur.qy;
+  if (edge) {
+    out.q = row_ref(k, c, ye);
+    pull_shift<S, M>(k, ye, col, out.f, out.h);
+    finish<R, M>(k, c, ye, col.xc, out);
+    qy_share[(w == 0 ? 0 : G + 1) * 64 + lane] = out.qy;
+  }
+  __syncthreads();
+  const R lo = qy_share[w * 64 + lane], hi = qy_share[(w + 2) * 64 + lane];
+  collide_store<S, M>(k, c, y, col, store, cur, R(0.5) * (hi - lo), xl, 0u);
+}
+
+template <int S, int M, int G>
+__global__ __launch_bounds__(64 * G) TCLBM_F32_OCC void row_group_kernel(KParams k) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);  // uniform: one group and tile per block
+  const int grp = b / k.n_xtiles;
+  const int xt = b - grp * k.n_xtiles;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ float lds[G * 2 * kLdsSlot];
+  __shared__ float qy_share[(G + 2) * 64];
+  row_group<S, M, G>(k, grp, xt, w, threadIdx.x & 63, (LdsF *)qy_share, (LdsF *)(lds + w * 2 * kLdsSlot));
+}
+
 // 16-bit storage: the stochastic-rounding stores need a few more registers;
 // capped to keep 3 waves per SIMD (a handful of spills)
 template <int S, int M>
@@ -925,7 +990,11 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
   const bool b = d && TCLBM_BUFFER_ADDR && buffer_fits(k, storage);
   switch (storage) {
     case kF32:
-      if (d && k.strip_rows == 1 && kStepWaves != 1)
+      if (d && k.strip_rows == 1 && kRowGroup > 1) {
+        const int groups = (k.ny + kRowGroup - 1) / kRowGroup;
+        hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup>), dim3(groups * k.n_xtiles), dim3(64 * kRowGroup),
+                           0, s, k);
+      } else if (d && k.strip_rows == 1 && kStepWaves != 1)
         hipLaunchKernelGGL((step_kernel<kF32, 1, 1>), dim3(waves), dim3(64), 0, s, k);
       else if (d) hipLaunchKernelGGL((step_kernel<kF32, 1, kStepWaves>), grid, block, 0, s, k);
       else hipLaunchKernelGGL((step_kernel<kF32, 0, kStepWaves>), grid, block, 0, s, k);
@@ -947,6 +1016,17 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+const char *step_kernel_name(const KParams &k, int storage) {
+  const bool d = TCLBM_SCHEME_SPECIAL && default_scheme(k);
+  switch (storage) {
+    case kF32: return (d && k.strip_rows == 1 && kRowGroup > 1) ? "row_group_kernel" : "step_kernel";
+    case kF16:
+    case kBF16: return "step_kernel_16";
+    case kF64: return "step_kernel_f64";
+    default: return "";
+  }
 }
 
 size_t store_bytes(int storage) {

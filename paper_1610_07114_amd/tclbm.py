@@ -53,7 +53,7 @@ class tclbm_sums(ctypes.Structure):
 
 EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_set_bc", "tclbm_step",
            "tclbm_step_timed", "tclbm_moments", "tclbm_steps_done", "tclbm_read_state", "tclbm_set_tuning",
-           "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
+           "tclbm_step_kernel", "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
            "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
            "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_set_strip_rows",
            "tclbm_batch_strip_rows", "tclbm_batch_destroy"]
@@ -87,6 +87,8 @@ def _load():
     lib.tclbm_moments.restype = ctypes.c_int
     lib.tclbm_steps_done.argtypes = [H]
     lib.tclbm_steps_done.restype = ctypes.c_int64
+    lib.tclbm_step_kernel.argtypes = [H]
+    lib.tclbm_step_kernel.restype = ctypes.c_char_p
     lib.tclbm_read_state.argtypes = [H, d]
     lib.tclbm_read_state.restype = ctypes.c_int
     lib.tclbm_set_tuning.argtypes = [H, ctypes.c_int32, ctypes.c_int32]
@@ -189,6 +191,10 @@ def tclbm_moments(h, nx: int, ny: int, fields: bool = True, check: bool = True):
 
 def tclbm_steps_done(h) -> int:
     return int(_lib.tclbm_steps_done(h))
+
+
+def tclbm_step_kernel(h) -> str:
+    return _lib.tclbm_step_kernel(h).decode()
 
 
 def tclbm_read_state(h, nplanes: int, nx: int, ny: int) -> np.ndarray:
@@ -306,6 +312,11 @@ class Lattice:
     @property
     def steps(self) -> int:
         return tclbm_steps_done(self.h)
+
+    @property
+    def kernel(self) -> str:
+        """Name of the kernel one step launches (as in a kernel trace)."""
+        return tclbm_step_kernel(self.h)
 
     def close(self):
         if self.h is not None:

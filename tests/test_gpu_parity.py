@@ -303,6 +303,43 @@ def test_batch_equals_members_alone_bitwise(T):
         lat.close()
 
 
+@pytest.mark.parametrize("label,make", [
+    ("rb 512x256, walls", lambda: W.rayleigh_benard(nx=512, ny=256, seed=3, noise=1e-3)),
+    ("rb 130x67, ny % 4 = 3", lambda: W.rayleigh_benard(nx=130, ny=67, seed=1, noise=1e-3)),
+    ("rb 100x14, one group between the wall groups", lambda: W.rayleigh_benard(nx=100, ny=14, seed=2, noise=1e-3)),
+    ("rb 70x9, every group touches a wall", lambda: W.rayleigh_benard(nx=70, ny=9, seed=4, noise=1e-3)),
+    ("noise 64x4 periodic, one group wrapping both ways", lambda: W.uniform_noise(64, 4, seed=5, ax=1e-5)),
+    ("noise 200x5 periodic, overhanging group", lambda: W.uniform_noise(200, 5, seed=6, ay=-2e-5)),
+    ("noise 63x3 periodic, no full group", lambda: W.uniform_noise(63, 3, seed=7)),
+    ("shock tube 700x8", lambda: W.shock_tube(nx=700, ny=8)),
+])
+def test_row_groups_equal_lone_rows_bitwise(T, label, make):
+    """FP32 lattices of single-row strips run four rows per block, the waves
+    sharing their rows' u_y(1 - theta) through LDS; the batch kernel runs every
+    row as a lone wave that pulls its neighbour rows itself.  The states agree
+    bit for bit after 40 steps."""
+    import torch
+    case = make()
+    say(f"case row groups vs lone rows fp32: {label}")
+    stream = torch.cuda.Stream()
+    a = T.Lattice(case, storage="f32", stream=stream)
+    a.set_tuning(1, 16)
+    assert a.kernel == "row_group_kernel"
+    a.step(40)
+    ref = a.read_state()
+    a.close()
+    lat = T.Lattice(case, storage="f32", stream=stream)
+    b = T.Batch([lat])
+    b.set_strip_rows(1)
+    b.set_graph_chunk(16)
+    b.step(40)
+    b.close()
+    got = lat.read_state()
+    lat.close()
+    assert np.all(np.isfinite(ref))
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("nx,ny,walls,storage", [
     (3, 3, False, "f64"),      # smallest periodic lattice: every neighbour wraps
     (3, 5, True, "f64"),       # smallest walled lattice (one fluid row between walls and edges)

@@ -38,6 +38,12 @@ def test_exports_every_declared_symbol(T):
     assert sorted(T.EXPORTS) == declared
 
 
+def test_null_handle_queries(T):
+    """Queries on a NULL handle answer without touching a device."""
+    assert T._lib.tclbm_step_kernel(None) is None
+    assert T._lib.tclbm_steps_done(None) == -1
+
+
 def test_state_bytes_plan(T):
     p = T.tclbm_default_params(512, 256)
     nb = T.tclbm_state_bytes(p)
