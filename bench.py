@@ -23,6 +23,9 @@ line also carries, measured in the same run:
                   same stream through the plain one-lattice-at-a-time FP32 path
   hbm_ceiling     a plain chunked 2 GiB copy on the same GPU; roofline_large
                   and batch also state their fraction of it
+  cpu_baseline_detail  the FP64 oracle on one thread and on all threads for the
+                  Couette, shock-tube and 512x256 Rayleigh-Benard workloads,
+                  with the host's CPU count and model
 """
 from __future__ import annotations
 
@@ -85,9 +88,9 @@ def load_traffic(path, key):
 
 
 # ------------------------------------------------------------------ CPU baseline ---
-def cpu_baseline(cases, seconds_target: float = 12.0, label=None):
-    """The FP64 oracle as it stands, on the host cores, over a bounded number of
-    steps of the given lattices (round robin, whole lattices)."""
+def _time_oracle(cases, seconds_target: float):
+    """Steps the FP64 oracle over the given lattices (round robin, whole
+    lattices) for about `seconds_target` seconds: (MLUPS, steps, seconds)."""
     import oracle as O
     lats = []
     for case in cases:
@@ -106,9 +109,52 @@ def cpu_baseline(cases, seconds_target: float = 12.0, label=None):
     for _, L in lats:
         L.step(n)
     dt = time.perf_counter() - t0
+    return nodes * n / dt / 1e6, n, dt
+
+
+def cpu_baseline(cases, seconds_target: float = 12.0, label=None):
+    """The FP64 oracle as it stands, on the host cores, over a bounded number of
+    steps of the given lattices (round robin, whole lattices)."""
+    import oracle as O
+    mlups, n, dt = _time_oracle(cases, seconds_target)
     what = label or f"{cases[0].name} {cases[0].nx}x{cases[0].ny}"
-    return {"value": round(nodes * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{what}, {n} steps from the seeded initial state, FP64, {dt:.1f} s"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_detail(seconds_target: float = 3.0) -> dict:
+    """The FP64 oracle on one thread and on all its threads for the Couette,
+    shock-tube and Rayleigh-Benard workloads (each timed over about
+    `seconds_target` seconds), with the host's CPU count and model."""
+    import oracle as O
+    full = O.num_threads()
+    out = {"nproc": os.cpu_count(), "cpu_model": cpu_model(), "unit": "MLUPS", "threads": sorted({1, full}),
+           "seconds_per_sample": seconds_target, "cases": {}}
+    try:
+        for name in ("couette", "shock", "rb"):
+            case, wname = workload_case(name)
+            row = {}
+            for t in out["threads"]:
+                O.set_num_threads(t)
+                mlups, n, _ = _time_oracle([case], seconds_target)
+                row[f"threads_{t}"] = round(mlups, 3)
+                row[f"steps_{t}"] = n
+            out["cases"][wname] = row
+    finally:
+        O.set_num_threads(full)
+    return out
 
 
 # ------------------------------------------------------------------- probes ---
@@ -421,6 +467,9 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline([case])
+        if args.workload == "rb" and not args.no_extras:
+            log("bench: FP64 oracle on one and on all host threads, configs 1-3")
+            out["cpu_baseline_detail"] = cpu_baseline_detail()
     print(json.dumps(out), flush=True)
 
 
