@@ -149,6 +149,12 @@ void fill_kparams(tclbm_ctx *c) {
   }
 }
 
+// Row-tiles per wave strip that the automatic strip height aims at, by storage
+// (one wave-row is one 62-column tile row; see decompose and batch_auto_rows).
+static long long strip_target(int storage) {
+  return (storage == kF32) ? 163840 : (storage == kF64 ? 65536 : 32768);
+}
+
 void decompose(tclbm_ctx *c) {
   KParams &k = c->k;
   const bool xper = k.bc[kXlo] == kPeriodic;
@@ -163,9 +169,7 @@ void decompose(tclbm_ctx *c) {
     // fastest for FP32 (2 rows: 1252 us, 3: 1180, 4: 1204, 8: 1237, 33: 1414)
     // while the 16-bit kernels prefer longer ones (FP16 4 rows: 919 us, 8: 839,
     // 12: 816).
-    const int st = c->p.storage;
-    const long long target = (st == kF32) ? 163840 : (st == kF64 ? 65536 : 32768);
-    long long r = ((long long)k.ny * k.n_xtiles) / target;
+    long long r = ((long long)k.ny * k.n_xtiles) / strip_target(c->p.storage);
     rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }
   if (rows > k.ny) rows = k.ny;
@@ -636,13 +640,13 @@ struct tclbm_batch {
   char err[256];
 };
 
-// Strip height for a whole batch: enough waves over all members to fill the
-// chip a few times (each wave-row is a 62-column tile row), long strips
-// otherwise, since every strip re-pulls its halo rows.
+// Strip height for a whole batch: the single-lattice rule applied to the
+// members' row-tiles together (256 uneven RB lattices: FP32 2 rows and FP16
+// 13 rows, the fastest heights measured for that batch), capped at 32.
 static int batch_auto_rows(const tclbm_batch *b) {
   long long rowtiles = 0;
   for (tclbm_handle h : b->m) rowtiles += (long long)h->k.ny * h->k.n_xtiles;
-  long long r = rowtiles / 32768;
+  long long r = rowtiles / strip_target(b->storage);
   return (int)(r < 1 ? 1 : (r > 32 ? 32 : r));
 }
 
