@@ -538,16 +538,21 @@ __device__ __forceinline__ void get_row_lds(const KParams &k, const Consts<float
   finish<float, M>(k, c, y, col.xc, s);
 }
 
-// State of the WALL row y whose fluid neighbour state is `in`.
+// State of the WALL row y whose fluid neighbour state is `in`.  issued: the
+// loads of its known populations were already issued into s.f, s.h (by
+// pull_issue; needed only when its density comes from them).
 template <int S, int M = 0>
 __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<typename Real<S>::T> &c, int y,
                                              const Col &col, const RowState<typename Real<S>::T> &in,
-                                             RowState<typename Real<S>::T> &s) {
+                                             RowState<typename Real<S>::T> &s, bool issued = false) {
   using R = typename Real<S>::T;
   const int side = (y == 0) ? kYlo : kYhi;
   const int yf = (y == 0) ? 1 : y - 1;
   s.q = row_ref(k, c, y);
-  if (flags<M>(k).wall_rho == 0) pull<S, M>(k, y, col, s.f, s.h);
+  if (flags<M>(k).wall_rho == 0) {
+    if (!issued) pull_issue<S, M>(k, y, col, s.f, s.h);
+    pull_shift<S, M>(k, y, col, s.f, s.h);
+  }
   R axI, ayI, axW, ayW;
   node_accel<R, M>(k, yf, col.xc, axI, ayI);
   node_accel<R, M>(k, y, col.xc, axW, ayW);
@@ -826,24 +831,35 @@ __global__ __launch_bounds__(64 * W) TCLBM_F32_OCC void step_kernel(KParams k) {
 }
 // Lattices of single-row strips, G consecutive rows of one tile column per
 // block, one wave per row.  A row's collision needs u_y(1 - theta) of the rows
-// above and below it (central difference), so a lone wave pulls three rows to
-// collide one.  In a group every wave pulls and finishes its own row, the first
-// and last wave also the row just outside the group, and the waves read their
-// neighbours' values from LDS: (G + 2) / G pulls per collided row instead of 3.
-// The arithmetic per node is that of the lone-wave path, value for value.
-// Groups that touch a non-periodic wall (the one-sided differences and wall
-// rows of the general march) or overhang the lattice run every row as a lone
-// wave.  The condition is the same for the whole block, so either all G waves
-// meet the barrier or none does.
-template <int S, int M, int G>
+// above and below it (central difference; one-sided at a non-periodic edge
+// row), so a lone wave pulls three rows to collide one.  In a group every wave
+// pulls and evaluates its own row and the waves read their neighbours' values
+// from LDS: (G + 2) / G pulls per collided row instead of 3.  The first and
+// last wave also pull the row just outside the group; in the group that holds
+// a non-periodic edge row, the edge row's wave pulls the row next to it
+// instead, which a WALL edge row is derived from (so the wall row is derived
+// once per group, not by two waves).  The arithmetic per node is that of the
+// lone-wave path, value for value.  Groups that overhang the lattice, or whose
+// outside rows are WALL rows, run every row as a lone wave; the choice is the
+// same for the whole block, so either all G waves meet the barrier or none does.
+// E: the lattice has non-periodic y sides (edge groups exist); lattices
+// periodic in y take the instantiation without the edge roles.
+template <int S, int M, int G, bool E>
 __device__ __forceinline__ void row_group(const KParams &k, int grp, int xt, int w, int lane,
                                           LdsF *qy_share, LdsF *lds) {
   static_assert(S == kF32, "row groups serve FP32 storage");
   using R = typename Real<S>::T;
   const int ny = k.ny;
   const int g0 = grp * G, y = g0 + w;
-  const bool yper = (k.bc[kYlo] == kPeriodic);
-  if (!(g0 + G <= ny && (yper || (g0 >= 3 && g0 + G <= ny - 3)))) {
+  const bool yper = !E || (k.bc[kYlo] == kPeriodic);  // E = false is launched for periodic y only
+  // 1: central differences only; 2: holds the bottom row; 3: holds the top row
+  int kind = 0;
+  if (g0 + G <= ny) {
+    if (yper || (g0 >= 1 && g0 + G <= ny - 1 && !is_wall_row(k, g0 - 1) && !is_wall_row(k, g0 + G))) kind = 1;
+    else if (E && G >= 3 && g0 == 0 && G <= ny - 2) kind = 2;  // one-sided: rows 1 and 2 in the group
+    else if (E && G >= 3 && g0 + G == ny && g0 >= 1 && !is_wall_row(k, g0 - 1)) kind = 3;
+  }
+  if (kind == 0) {
     if (y < ny) march<S, M>(k, y * k.n_xtiles + xt, lane, lds);  // strip y of one row
     return;
   }
@@ -851,27 +867,44 @@ __device__ __forceinline__ void row_group(const KParams &k, int grp, int xt, int
   const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
   const Col col = make_col(k, xl);
   const Consts<R> c = make_consts<R, M>(k);
-  const bool edge = (w == 0) || (w == G - 1);  // wave-uniform
-  const int ye = (w == 0) ? (y == 0 ? ny - 1 : y - 1) : (y == ny - 1 ? 0 : y + 1);
+  // wave-uniform roles
+  const bool edge_lo = E && (kind == 2 && w == 0), edge_hi = E && (kind == 3 && w == G - 1);
+  const bool halo_lo = (w == 0 && kind != 2), halo_hi = (w == G - 1 && kind != 3);
+  const bool wall = E && (edge_lo || edge_hi) && is_wall_row(k, y);
+  const bool other = halo_lo || halo_hi || wall;  // a second row: outside the group, or the wall's neighbour
+  const int yo = halo_lo ? (y == 0 ? ny - 1 : y - 1) : halo_hi ? (y == ny - 1 ? 0 : y + 1) : (edge_lo ? 1 : ny - 2);
   RowState<R> cur, out;
-  pull_issue<S, M>(k, y, col, cur.f, cur.h);
-  if (edge) pull_issue<S, M>(k, ye, col, out.f, out.h);
-  cur.q = row_ref(k, c, y);
-  pull_shift<S, M>(k, y, col, cur.f, cur.h);
-  finish<R, M>(k, c, y, col.xc, cur);
-  qy_share[(w + 1) * 64 + lane] = cur.qy;
-  if (edge) {
-    out.q = row_ref(k, c, ye);
-    pull_shift<S, M>(k, ye, col, out.f, out.h);
-    finish<R, M>(k, c, ye, col.xc, out);
-    qy_share[(w == 0 ? 0 : G + 1) * 64 + lane] = out.qy;
+  if (!wall || flags<M>(k).wall_rho == 0) pull_issue<S, M>(k, y, col, cur.f, cur.h);
+  if (other) pull_issue<S, M>(k, yo, col, out.f, out.h);
+  if (other) {
+    out.q = row_ref(k, c, yo);
+    pull_shift<S, M>(k, yo, col, out.f, out.h);
+    finish<R, M>(k, c, yo, col.xc, out);
   }
+  if (E && wall) {
+    get_wall_row<S, M>(k, c, y, col, out, cur, true);
+  } else {
+    cur.q = row_ref(k, c, y);
+    pull_shift<S, M>(k, y, col, cur.f, cur.h);
+    finish<R, M>(k, c, y, col.xc, cur);
+  }
+  qy_share[(w + 1) * 64 + lane] = cur.qy;  // slot s: row g0 + s - 1
+  if (halo_lo) qy_share[lane] = out.qy;
+  if (halo_hi) qy_share[(G + 1) * 64 + lane] = out.qy;
   __syncthreads();
-  const R lo = qy_share[w * 64 + lane], hi = qy_share[(w + 2) * 64 + lane];
-  collide_store<S, M>(k, c, y, col, store, cur, R(0.5) * (hi - lo), xl, 0u);
+  R Dy;
+  if (E && edge_lo) {
+    Dy = R(0.5) * (R(-3) * cur.qy + R(4) * qy_share[2 * 64 + lane] - qy_share[3 * 64 + lane]);
+  } else if (E && edge_hi) {
+    Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_share[(G - 1) * 64 + lane] + qy_share[(G - 2) * 64 + lane]);
+  } else {
+    const R lo = qy_share[w * 64 + lane], hi = qy_share[(w + 2) * 64 + lane];
+    Dy = R(0.5) * (hi - lo);
+  }
+  collide_store<S, M>(k, c, y, col, store, cur, Dy, xl, 0u);
 }
 
-template <int S, int M, int G>
+template <int S, int M, int G, bool E>
 __global__ __launch_bounds__(64 * G) TCLBM_F32_OCC void row_group_kernel(KParams k) {
   const int b = xcd_block(blockIdx.x, gridDim.x);  // uniform: one group and tile per block
   const int grp = b / k.n_xtiles;
@@ -879,7 +912,7 @@ __global__ __launch_bounds__(64 * G) TCLBM_F32_OCC void row_group_kernel(KParams
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   __shared__ float lds[G * 2 * kLdsSlot];
   __shared__ float qy_share[(G + 2) * 64];
-  row_group<S, M, G>(k, grp, xt, w, threadIdx.x & 63, (LdsF *)qy_share, (LdsF *)(lds + w * 2 * kLdsSlot));
+  row_group<S, M, G, E>(k, grp, xt, w, threadIdx.x & 63, (LdsF *)qy_share, (LdsF *)(lds + w * 2 * kLdsSlot));
 }
 
 // 16-bit storage: the stochastic-rounding stores need a few more registers;
@@ -992,8 +1025,12 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
     case kF32:
       if (d && k.strip_rows == 1 && kRowGroup > 1) {
         const int groups = (k.ny + kRowGroup - 1) / kRowGroup;
-        hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup>), dim3(groups * k.n_xtiles), dim3(64 * kRowGroup),
-                           0, s, k);
+        if (k.bc[kYlo] == kPeriodic)
+          hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, false>), dim3(groups * k.n_xtiles),
+                             dim3(64 * kRowGroup), 0, s, k);
+        else
+          hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, true>), dim3(groups * k.n_xtiles),
+                             dim3(64 * kRowGroup), 0, s, k);
       } else if (d && k.strip_rows == 1 && kStepWaves != 1)
         hipLaunchKernelGGL((step_kernel<kF32, 1, 1>), dim3(waves), dim3(64), 0, s, k);
       else if (d) hipLaunchKernelGGL((step_kernel<kF32, 1, kStepWaves>), grid, block, 0, s, k);

@@ -5,6 +5,7 @@ bounds stated per test.  Relative L-inf: rho and T against their max; u
 against max(max |u_oracle|, U) with U the problem's characteristic velocity
 (flows that start at rest have tiny max |u| at first).  Sizes span several
 tiles and strips with ragged tails."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -312,12 +313,19 @@ def test_batch_equals_members_alone_bitwise(T):
     ("noise 200x5 periodic, overhanging group", lambda: W.uniform_noise(200, 5, seed=6, ay=-2e-5)),
     ("noise 63x3 periodic, no full group", lambda: W.uniform_noise(63, 3, seed=7)),
     ("shock tube 700x8", lambda: W.shock_tube(nx=700, ny=8)),
+    ("noise 96x12, bounce-back y walls (pulled edge rows)",
+     lambda: dataclasses.replace(W.uniform_noise(96, 12, seed=8),
+                                 bc=(W.PERIODIC, W.PERIODIC, W.BOUNCEBACK, W.BOUNCEBACK))),
+    ("rb 100x16, adiabatic bottom wall", lambda: dataclasses.replace(
+        W.rayleigh_benard(nx=100, ny=16, seed=9, noise=1e-3), bc=(W.PERIODIC, W.PERIODIC, W.WALL_ADIABATIC, W.WALL))),
+    ("rb 64x6, bottom edge group, top rows alone", lambda: W.rayleigh_benard(nx=64, ny=6, seed=10, noise=1e-3)),
 ])
 def test_row_groups_equal_lone_rows_bitwise(T, label, make):
     """FP32 lattices of single-row strips run four rows per block, the waves
-    sharing their rows' u_y(1 - theta) through LDS; the batch kernel runs every
-    row as a lone wave that pulls its neighbour rows itself.  The states agree
-    bit for bit after 40 steps."""
+    sharing their rows' u_y(1 - theta) through LDS (also in the groups that hold
+    a wall or bounce-back edge row); the batch kernel runs every row as a lone
+    wave that pulls its neighbour rows itself.  The states agree bit for bit
+    after 40 steps."""
     import torch
     case = make()
     say(f"case row groups vs lone rows fp32: {label}")
