@@ -819,8 +819,9 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
   }
 }
 
-// W waves per block: kStepWaves, or 1 for lattices of single-row strips (their
-// 2-3 waves per SIMD then spread evenly over the CUs: 512x256 10.4 -> 10.2 us).
+// W waves per block: kStepWaves, or 1 for default-scheme lattices of single-row
+// strips when row groups are switched off (their 2-3 waves per SIMD then spread
+// evenly over the CUs: 512x256 10.4 -> 10.2 us).
 template <int S, int M, int W>
 __global__ __launch_bounds__(64 * W) TCLBM_F32_OCC void step_kernel(KParams k) {
   // wave-uniform: rows, strips and table reads stay scalar
