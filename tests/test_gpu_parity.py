@@ -304,6 +304,27 @@ def test_batch_equals_members_alone_bitwise(T):
         lat.close()
 
 
+def test_step_kernel_names(T):
+    """tclbm_step_kernel names the kernel that a step launches, as a kernel
+    trace shows it, for each storage form and launch shape."""
+    import torch
+    stream = torch.cuda.Stream()
+    case = W.rayleigh_benard(nx=130, ny=40, seed=1, noise=1e-3)
+    expect = [("f32", 1, "row_group_kernel"), ("f32", 3, "step_kernel"), ("f16", 0, "step_kernel_16"),
+              ("bf16", 2, "step_kernel_16"), ("f64", 0, "step_kernel_f64")]
+    for storage, rows, name in expect:
+        lat = T.Lattice(case, storage=storage, stream=stream)
+        lat.set_tuning(rows, 16)
+        assert lat.kernel == name, (storage, rows, lat.kernel)
+        lat.step(2)
+        lat.close()
+    generic = W.taylor_green(N=64)          # per-node force field: the generic scheme
+    lat = T.Lattice(generic, storage="f32", stream=stream)
+    lat.set_tuning(1, 16)
+    assert lat.kernel == "step_kernel"
+    lat.close()
+
+
 @pytest.mark.parametrize("label,make", [
     ("rb 512x256, walls", lambda: W.rayleigh_benard(nx=512, ny=256, seed=3, noise=1e-3)),
     ("rb 130x67, ny % 4 = 3", lambda: W.rayleigh_benard(nx=130, ny=67, seed=1, noise=1e-3)),
