@@ -328,8 +328,8 @@ def test_step_kernel_names(T):
 @pytest.mark.parametrize("label,make", [
     ("rb 512x256, walls", lambda: W.rayleigh_benard(nx=512, ny=256, seed=3, noise=1e-3)),
     ("rb 130x67, ny % 4 = 3", lambda: W.rayleigh_benard(nx=130, ny=67, seed=1, noise=1e-3)),
-    ("rb 100x14, one group between the wall groups", lambda: W.rayleigh_benard(nx=100, ny=14, seed=2, noise=1e-3)),
-    ("rb 70x9, every group touches a wall", lambda: W.rayleigh_benard(nx=70, ny=9, seed=4, noise=1e-3)),
+    ("rb 100x14, bottom edge group, two interior groups, top rows alone", lambda: W.rayleigh_benard(nx=100, ny=14, seed=2, noise=1e-3)),
+    ("rb 70x9, bottom edge group, the rest alone (outside row a wall)", lambda: W.rayleigh_benard(nx=70, ny=9, seed=4, noise=1e-3)),
     ("noise 64x4 periodic, one group wrapping both ways", lambda: W.uniform_noise(64, 4, seed=5, ax=1e-5)),
     ("noise 200x5 periodic, overhanging group", lambda: W.uniform_noise(200, 5, seed=6, ay=-2e-5)),
     ("noise 63x3 periodic, no full group", lambda: W.uniform_noise(63, 3, seed=7)),
@@ -340,6 +340,11 @@ def test_step_kernel_names(T):
     ("rb 100x16, adiabatic bottom wall", lambda: dataclasses.replace(
         W.rayleigh_benard(nx=100, ny=16, seed=9, noise=1e-3), bc=(W.PERIODIC, W.PERIODIC, W.WALL_ADIABATIC, W.WALL))),
     ("rb 64x6, bottom edge group, top rows alone", lambda: W.rayleigh_benard(nx=64, ny=6, seed=10, noise=1e-3)),
+    ("rb 70x8, a bottom and a top edge group only", lambda: W.rayleigh_benard(nx=70, ny=8, seed=11, noise=1e-3)),
+    ("rb 70x12, bottom, interior and top groups", lambda: W.rayleigh_benard(nx=70, ny=12, seed=12, noise=1e-3)),
+    ("noise 64x8, bounce-back y, two edge groups",
+     lambda: dataclasses.replace(W.uniform_noise(64, 8, seed=13),
+                                 bc=(W.PERIODIC, W.PERIODIC, W.BOUNCEBACK, W.BOUNCEBACK))),
 ])
 def test_row_groups_equal_lone_rows_bitwise(T, label, make):
     """FP32 lattices of single-row strips run four rows per block, the waves
