@@ -81,6 +81,8 @@ def lib():
         _lib.orc_init.restype = ctypes.c_int
         _lib.orc_macros.argtypes = [P, d, d, d, d, d, d]
         _lib.orc_macros.restype = ctypes.c_int
+        _lib.orc_gradients.argtypes = [P, d, d, d, d]
+        _lib.orc_gradients.restype = ctypes.c_int
         _lib.orc_step.argtypes = [P, d, d, ctypes.c_int64]
         _lib.orc_step.restype = ctypes.c_int
         _lib.orc_check_params.argtypes = [P]
@@ -248,6 +250,17 @@ class Lattice:
             raise RuntimeError(f"orc_step failed ({rc})")
         self.steps += n
         return self
+
+    def gradients(self):
+        """(Dx, Dy), each [ny, nx]: the correction-term derivatives
+        d/dx[u_x (1 - theta)], d/dy[u_y (1 - theta)] (Section 4) that the next
+        collision of the current state uses."""
+        ny, nx = self.params.ny, self.params.nx
+        out = [np.zeros((ny, nx)) for _ in range(2)]
+        rc = lib().orc_gradients(ctypes.byref(self._c), _p(self.f), _p(self.h), *[_p(v) for v in out])
+        if rc:
+            raise RuntimeError(f"orc_gradients failed ({rc})")
+        return tuple(out)
 
     def macros(self):
         """(rho, ux, uy, T), each [ny, nx]."""

@@ -660,6 +660,64 @@ int orc_macros(const orc_params *p, const double *f_in, const double *h_in, doub
   return 0;
 }
 
+/* Macroscopic fields and Q = u (1 - theta), theta = T/T0, of a state whose
+ * wall nodes have already been extrapolated (Section 4's correction needs Q). */
+static void macro_fields(const orc_params *p, const double *f, const double *h, double *Rho, double *Ux,
+                         double *Uy, double *Tt, double *Qx, double *Qy) {
+  const long n = (long)p->nx * p->ny;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < n; ++i) {
+    double fb[9], hb[9];
+    for (int a = 0; a < 9; ++a) {
+      fb[a] = f[a * n + i];
+      hb[a] = h[a * n + i];
+    }
+    orc_node_macros(p, fb, hb, node_ax(p, i), node_ay(p, i), &Rho[i], &Ux[i], &Uy[i], &Tt[i]);
+    double theta = Tt[i] / p->T0;
+    Qx[i] = Ux[i] * (1.0 - theta);
+    Qy[i] = Uy[i] * (1.0 - theta);
+  }
+}
+
+/* Section 4: Dx = d/dx[u_x (1 - theta)] and Dy = d/dy[u_y (1 - theta)] at node
+ * (x, y) from the Q fields, by second-order differences (central in the bulk
+ * and across periodic wraps, one-sided on non-periodic edges). */
+static void node_gradients(const orc_params *p, const double *Qx, const double *Qy, int x, int y, double *Dx,
+                           double *Dy) {
+  const int nx = p->nx, ny = p->ny;
+  const int xper = p->bc[ORC_XLO] == ORC_PERIODIC, yper = p->bc[ORC_YLO] == ORC_PERIODIC;
+  *Dx = deriv(Qx + IDX(0, y), x, nx, 1, xper);
+  *Dy = deriv(Qy + x, y, ny, nx, yper);
+}
+
+/* The correction gradients Dx, Dy (nx*ny each, index y*nx + x) that the next
+ * collision of the state (f_in, h_in) uses: walls extrapolated first, as in
+ * orc_step. */
+int orc_gradients(const orc_params *p, const double *f_in, const double *h_in, double *Dx, double *Dy) {
+  if (orc_check_params(p)) return 1;
+  const int nx = p->nx, ny = p->ny;
+  const long n = (long)nx * ny;
+  double *f = (double *)malloc(sizeof(double) * 9 * n);
+  double *h = (double *)malloc(sizeof(double) * 9 * n);
+  double *mr = (double *)malloc(sizeof(double) * 6 * n);
+  if (!f || !h || !mr) {
+    free(f);
+    free(h);
+    free(mr);
+    return 2;
+  }
+  memcpy(f, f_in, sizeof(double) * 9 * n);
+  memcpy(h, h_in, sizeof(double) * 9 * n);
+  wall_prestep(p, f, h);
+  macro_fields(p, f, h, mr, mr + n, mr + 2 * n, mr + 3 * n, mr + 4 * n, mr + 5 * n);
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) node_gradients(p, mr + 4 * n, mr + 5 * n, x, y, &Dx[IDX(x, y)], &Dy[IDX(x, y)]);
+  free(f);
+  free(h);
+  free(mr);
+  return 0;
+}
+
 /* nsteps full time steps, in place on (f, h).  Step order: walls, macroscopic
  * variables, gradients of u(1 - theta), collision of f and h, pull streaming. */
 int orc_step(const orc_params *p, double *f, double *h, int64_t nsteps) {
@@ -683,26 +741,15 @@ int orc_step(const orc_params *p, double *f, double *h, int64_t nsteps) {
     wall_prestep(p, f, h);
 
     /* 1. macroscopic variables, and Q = u (1 - theta) with theta = T/T0 */
-#pragma omp parallel for schedule(static)
-    for (long i = 0; i < n; ++i) {
-      double fb[9], hb[9];
-      for (int a = 0; a < 9; ++a) {
-        fb[a] = f[a * n + i];
-        hb[a] = h[a * n + i];
-      }
-      orc_node_macros(p, fb, hb, node_ax(p, i), node_ay(p, i), &Rho[i], &Ux[i], &Uy[i], &Tt[i]);
-      double theta = Tt[i] / p->T0;
-      Qx[i] = Ux[i] * (1.0 - theta);
-      Qy[i] = Uy[i] * (1.0 - theta);
-    }
+    macro_fields(p, f, h, Rho, Ux, Uy, Tt, Qx, Qy);
 
     /* 2-4. gradients and collision */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         long i = IDX(x, y);
-        double Dx = deriv(Qx + IDX(0, y), x, nx, 1, xper);
-        double Dy = deriv(Qy + x, y, ny, nx, yper);
+        double Dx, Dy;
+        node_gradients(p, Qx, Qy, x, y, &Dx, &Dy);
         double fb[9], hb[9], fo[9], ho[9];
         for (int a = 0; a < 9; ++a) {
           fb[a] = f[a * n + i];
