@@ -1,28 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the fused TCLBM step on one MI355X.
 
-One "step" is one time step of the whole hot path over the lattice: pull
-streaming, wall treatment, macroscopic variables, correction gradients,
-cascaded collision of f with force and correction sources, energy-DF collision
-with the coupling source, store (one fused kernel), plus the FP64 Nusselt/mass
-reduction every `--reduce-every` steps.  Inputs are seeded and synthetic and
-resident in HBM before timing starts.
+One "step" is one time step of the whole hot path over every lattice of the
+workload: pull streaming, wall treatment, macroscopic variables, correction
+gradients, cascaded collision of f with force and correction sources,
+energy-DF collision with the coupling source, store (one fused kernel per step
+for all lattices), plus the FP64 reductions (mass, energy, Nusselt numerator)
+every `--reduce-every` steps.  Inputs are seeded and synthetic and resident in
+HBM before timing starts.
 
-Prints one JSON line on stdout.  `value` is the MLUPS of the selected workload
-(whole job, wall clock); `roofline` is the HBM roofline of its step kernel
-(algorithmic bytes per launch / average launch time from HIP events on the
-library's stream); `cpu_baseline` is the FP64 CPU reference timed on a bounded
-sample of the same workload on the host cores.  With the default workload the
-line also carries, measured in the same run:
-  roofline_large  the step kernel on an 8192x4096 lattice (HBM-resident state)
-  batch           256 seeded uneven Rayleigh-Benard lattices advanced by one
-                  launch per step, autotuned, aggregate MLUPS and roofline
-  serving         a seeded Poisson stream of RB/Couette solve requests served
-                  with continuous batching and 16-bit storage (solves/s,
-                  p50/p99 latency, Nu error against stored FP64 values), and the
-                  same stream through the plain one-lattice-at-a-time FP32 path
-  hbm_ceiling     a plain chunked 2 GiB copy on the same GPU; roofline_large
-                  and batch also state their fraction of it
+Prints one JSON line on stdout.  The default workload is the batched
+Rayleigh-Benard configuration: 256 seeded uneven 2N x N lattices (N
+log-uniform on [32, 512], Ra log-uniform on [1e4, 1e6], Pr uniform on
+[0.5, 7], FP32 storage) advanced together by one launch per step, replayed
+from HIP graphs, with the launch shape picked by the autotuner during the
+warm-up.  `value` is its whole-job MLUPS (wall clock around exactly --steps
+steps); `roofline` is the HBM roofline of its kernel (algorithmic bytes per
+launch / average launch time from HIP events on the batch's stream over the
+timed steps); `cpu_baseline` is the FP64 CPU reference timed on the host cores
+over a bounded sample of the same batch.  The line also carries, measured in
+the same run (unless --no-extras):
+  rb512x256       the single 512x256 Rayleigh-Benard lattice (cache-resident)
+  shock_tube      the 8192x4 shock tube
+  roofline_large  the step kernel on an 8192x4096 lattice (HBM-resident
+                  state) with FP32, FP16 and BF16 storage
+  hbm_ceiling     a plain chunked 2 GiB copy on the same GPU; the HBM-resident
+                  figures also state their fraction of it
+  serving         seeded Poisson streams of RB/Couette solve requests served
+                  with continuous batching and FP16 or BF16 storage (solves/s,
+                  p50/p99 latency, Nu error of requests restarted from FP64
+                  steady states), and the same stream through the plain
+                  one-lattice-at-a-time FP32 path
   cpu_baseline_detail  the FP64 oracle on one thread and on all threads for the
                   Couette, shock-tube and 512x256 Rayleigh-Benard workloads,
                   with the host's CPU count and model
@@ -41,6 +49,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 GOLDEN_BATCH_NU = os.path.join(ROOT, "tests", "golden", "rb_batch_nu_fp64.json")
+GOLDEN_STEADY_FIELDS = os.path.join(ROOT, "tests", "golden", "rb_batch_steady_fields.npz")
 
 
 def log(*a):
@@ -217,39 +226,64 @@ def bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, strip
 
 
 # -------------------------------------------------------------------- batch ---
-def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, strip_rows=0, graph_chunk=None,
-                traffic_json=None):
+def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, reduce_every=1000,
+                strip_rows=0, graph_chunk=None, traffic_json=None):
     """The batched workload: n seeded 2N x N Rayleigh-Benard lattices (N
     log-uniform on [32, 512], Ra log-uniform on [1e4, 1e6], Pr uniform on
-    [0.5, 7]) advanced together, one launch per step, HIP-graph chunks.  The
+    [0.5, 7]; draws below the scheme's linear stability limit 1/w1 = 0.55 are
+    drawn again) advanced together, one launch per step, HIP-graph chunks.  The
     autotuner's trial steps (strip height x graph chunk) are part of the
     warm-up; a given strip height (and graph chunk) replaces the autotuner.
-    `traffic` is the stored counter measurement for the strip height in use."""
+    The graph chunk is capped at half the timed steps, so that the timed steps
+    replay graphs.  Timed: exactly `steps` steps, with the FP64 sums of every
+    member after each `reduce_every` of them; HIP events on the batch's stream
+    bracket the same steps.  `traffic` is the stored counter measurement for
+    the strip height in use."""
     from paper_1610_07114_amd import serving as S
     from paper_1610_07114_amd import workloads as W
-    specs = W.batched_rb_specs(n, seed=seed)
+    rejected = []
+    specs = W.batched_rb_specs(n, seed=seed, rejected=rejected)
     t0 = time.perf_counter()
     cases = [W.rb_from_spec(s) for s in specs]
     nodes = sum(c.nx * c.ny for c in cases)
-    stream = torch.cuda.Stream(torch.device("cuda:0"))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
     lats = [tclbm.Lattice(c, storage=storage, stream=stream) for c in cases]
     del cases
-    log(f"batch: {n} seeded lattices resident ({time.perf_counter() - t0:.1f} s)")
+    log(f"batch: {n} seeded lattices resident, {nodes} nodes ({time.perf_counter() - t0:.1f} s; "
+        f"{len(rejected)} draws below the stability limit drawn again)")
     b = tclbm.Batch(lats)
     tune = None
     if strip_rows > 0:
         b.set_strip_rows(strip_rows)
-        if graph_chunk is not None:
-            b.set_graph_chunk(graph_chunk)
+        chunk = graph_chunk if graph_chunk is not None else 16
     else:
         tune = S.autotune_batch(b, log=log)
         log(f"batch autotune: {tune}")
+        chunk = tune["graph_chunk"]
+    cap = (steps // 2) // 2 * 2
+    chunk = min(chunk, cap) if cap >= 2 else 0
+    b.set_graph_chunk(chunk)
     rows_in_use = b.strip_rows
     b.step(warmup)
-    stream.synchronize()
+    torch.cuda.synchronize(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reductions = 0
     t0 = time.perf_counter()
-    ms = b.step_timed(steps)
+    ev0.record(stream)
+    done = 0
+    while done < steps:
+        k = min(reduce_every, steps - done)
+        b.step(k)
+        done += k
+        if done % reduce_every == 0:
+            for lat in lats:   # FP64 sums (mass, energy, Nusselt numerator)
+                tclbm.tclbm_moments(lat.h, lat.case.nx, lat.case.ny, fields=False, check=False)
+            reductions += 1
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
     waves = b.waves
     b.close()
     unstable = 0
@@ -257,107 +291,138 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
         _, _, _, _, _, st = tclbm.tclbm_moments(lat.h, lat.case.nx, lat.case.ny, fields=False, check=False)
         unstable += st != tclbm.OK
         lat.close()
-    avg = ms / 1e3 / steps
     bpl = bytes_per_lup(storage)
     return {"workload": f"batched_rayleigh_benard_{n}x(2N x N, N log-uniform 32..512, seed {seed})",
             "instances": n, "nodes": nodes, "storage": storage, "steps": steps, "warmup": warmup,
             "mlups": round(nodes * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+            "device_ms": round(dev_ms, 3), "graph_chunk": chunk, "fp64_reductions_timed": reductions,
             "autotune": tune, "waves_per_step": waves, "unstable_instances": int(unstable),
-            "strip_rows": rows_in_use,
-            "roofline": roofline(bpl, nodes, avg,
+            "redrawn_below_stability_limit": len(rejected), "strip_rows": rows_in_use,
+            "roofline": roofline(bpl, nodes, dev_ms / 1e3 / steps,
                                  load_traffic(traffic_json, f"batched_rayleigh_benard_{n}_{storage}_rows{rows_in_use}")
                                  if traffic_json else None, kernel="batch_step_kernel")}
 
 
 # ------------------------------------------------------------------ serving ---
-def golden_requests(S, start_id, rate_span, seed=7):
-    """Requests for the instances whose FP64 Nusselt history is stored, at
-    seeded arrival times inside the stream; their run lengths equal the stored
-    schedule so the final Nu can be compared with the FP64 value."""
+def restart_requests(S, start_id, rate_span, seed=7, time_units=30.0):
+    """Requests that restart the batched-subset instances whose FP64 oracle Nu
+    ended steady from the oracle's final fields (populations rebuilt at
+    equilibrium), at seeded arrival times inside the stream, for `time_units`
+    flow times.  Starting on the FP64 steady state fixes the roll pattern, so
+    the final Nu measures the storage precision; the reference is the stored
+    FP64 time average."""
     import numpy as np
     try:
         g = json.load(open(GOLDEN_BATCH_NU))
+        fields = np.load(GOLDEN_STEADY_FIELDS, allow_pickle=False)
     except Exception:
         return [], {}
     rng = np.random.default_rng(seed)
     out, ref = [], {}
     for k, inst in enumerate(g["instances"]):
-        # only histories that ended steady: their final value is the steady Nu
-        if not (inst["steps"] and inst["steps"][-1] == inst["total"] and math.isfinite(inst["nu_mean"])
-                and inst["unsteadiness"] < 2e-3):
+        if not (math.isfinite(inst["nu_mean"]) and inst["unsteadiness"] < 2e-3
+                and f"i{inst['index']}_rho" in fields):
             continue
         s = inst["spec"]
         rid = start_id + k
-        out.append(S.Request(rid, "rb", s["nx"], s["ny"], s["Ra"], s["Pr"], inst["total"],
-                             float(rng.uniform(0, rate_span)), s["seed"]))
-        ref[rid] = inst["nu"][-1]
+        init = {q: np.array(fields[f"i{inst['index']}_{q}"]) for q in ("rho", "ux", "uy", "T")}
+        out.append(S.Request(rid, "rb", s["nx"], s["ny"], s["Ra"], s["Pr"], S.solve_steps("rb", s["ny"], time_units),
+                             float(rng.uniform(0, rate_span)), s["seed"], init=init))
+        ref[rid] = inst["nu_mean"]
     return out, ref
 
 
-def bench_serving(torch, tclbm, n_requests=500, storage="f16", seed=0, load=0.8, time_units=1.0,
-                  sequential_fp32=True):
-    from paper_1610_07114_amd import serving as S
+def _nu_errors(res, ref):
     import numpy as np
-    # capacity: the aggregate lattice-update rate of a closed-loop run
-    # (everything queued at t = 0) of a calibration stream from the same
-    # distribution, divided by the mean work of the stream's own requests
-    # (the work per request is heavy-tailed, ~N^3, so counting solves of a
-    # different sample would misjudge it)
-    calib = S.make_requests(max(40, n_requests // 8), rate=1.0, seed=seed + 1000, time_units=time_units)
-    for r in calib:
-        r.arrival = 0.0
-    srv = S.Server(storage=storage)
-    t0 = time.perf_counter()
-    res = srv.run(calib, realtime=False)
-    cap_wall = time.perf_counter() - t0
-    cal_lups = sum(r.nx * r.ny * r.steps for r in res) / cap_wall
-    reqs = S.make_requests(n_requests, rate=1.0, seed=seed, time_units=time_units)
-    mean_work = sum(r.nx * r.ny * r.steps for r in reqs) / len(reqs)
-    capacity = cal_lups / mean_work
-    rate = load * capacity
-    reqs = S.make_requests(n_requests, rate=rate, seed=seed, time_units=time_units)
-    span = reqs[-1].arrival
-    gold, ref = golden_requests(S, n_requests, span)
-    reqs = sorted(reqs + gold, key=lambda r: r.arrival)
-    log(f"serving: closed loop {cal_lups / 1e6:.0f} MLUPS ({len(calib)} calibration requests, {cap_wall:.1f} s), "
-        f"mean work {mean_work:.3g} LUP -> capacity {capacity:.2f} solves/s; "
-        f"stream of {len(reqs)} requests at {rate:.2f}/s over {span:.1f} s")
-    t0 = time.perf_counter()
-    res = srv.run(reqs, realtime=True)
-    wall = time.perf_counter() - t0
-    # latency and throughput of the stream itself; the long Nu-check requests
-    # ride along and are reported by their error only
-    summ = S.summarize([r for r in res if r.rid not in ref], wall)
     errs = [abs(r.nu - ref[r.rid]) / abs(ref[r.rid]) for r in res if r.rid in ref]
-    out = {"storage": storage, "arrival_rate_per_s": round(rate, 3), "load_vs_capacity": load,
-           "capacity_solves_per_s": round(capacity, 3), "closed_loop_mlups": round(cal_lups / 1e6, 1),
-           "mean_work_lup": round(mean_work), **summ,
-           "run_length": f"{time_units} H/u_c per request (u_c = 0.08 RB, u0 = 0.05 Couette); "
-                         f"{len(gold)} more requests with a stored steady FP64 Nu run their stored length "
-                         f"(120 H/u_c) and are excluded from the latency figures",
-           "phases_s": {k: round(v, 2) for k, v in srv.phase_s.items()}, "rebatches": srv.rebatches,
-           "nu_rel_err_vs_fp64": {"max": max(errs) if errs else None, "n": len(errs),
-                                  "median": float(np.median(errs)) if errs else None}}
+    return {"max": max(errs) if errs else None, "median": float(np.median(errs)) if errs else None, "n": len(errs)}
+
+
+def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=0.8, time_units=1.0,
+                  sequential_fp32=True):
+    """One seeded Poisson stream of `n_requests` RB/Couette solves per storage
+    form, at `load` times the capacity measured in a closed-loop calibration
+    run of the same distribution, served with continuous batching; plus the
+    restart requests (Nu error), which are excluded from the latency figures.
+    Optionally the same stream through the plain one-lattice-at-a-time FP32
+    path."""
+    from paper_1610_07114_amd import serving as S
+    out = {"run_length": f"{time_units} H/u_c per request (u_c = 0.08 RB, u0 = 0.05 Couette)"}
+    reqs_unit = S.make_requests(n_requests, rate=1.0, seed=seed, time_units=time_units)
+    work = S.mean_work(reqs_unit)
+    work_c4 = S.mean_work(S.make_requests(n_requests, rate=1.0, seed=seed, time_units=50.0))
+    nu_fp32 = None
+    for storage in storages:
+        # capacity: the aggregate lattice-update rate of a closed-loop run
+        # (everything queued at t = 0) of a calibration stream from the same
+        # distribution, divided by the mean work of the stream's own requests
+        # (the work per request is heavy-tailed, ~N^3)
+        calib = S.make_requests(max(40, n_requests // 8), rate=1.0, seed=seed + 1000, time_units=time_units)
+        for r in calib:
+            r.arrival = 0.0
+        srv = S.Server(storage=storage)
+        t0 = time.perf_counter()
+        res = srv.run(calib, realtime=False)
+        cap_wall = time.perf_counter() - t0
+        cal_lups = sum(r.nx * r.ny * r.steps for r in res) / cap_wall
+        capacity = cal_lups / work
+        rate = load * capacity
+        reqs = S.make_requests(n_requests, rate=rate, seed=seed, time_units=time_units)
+        span = reqs[-1].arrival
+        gold, ref = restart_requests(S, n_requests, span)
+        reqs = sorted(reqs + gold, key=lambda r: r.arrival)
+        log(f"serving {storage}: closed loop {cal_lups / 1e6:.0f} MLUPS ({len(calib)} calibration requests, "
+            f"{cap_wall:.1f} s), mean work {work:.3g} LUP -> capacity {capacity:.2f} solves/s; stream of "
+            f"{len(reqs)} requests at {rate:.2f}/s over {span:.1f} s")
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        wall = time.perf_counter() - t0
+        summ = S.summarize([r for r in res if r.rid not in ref], wall)
+        out[storage] = {"arrival_rate_per_s": round(rate, 3), "load_vs_capacity": load,
+                        "capacity_solves_per_s": round(capacity, 3), "closed_loop_mlups": round(cal_lups / 1e6, 1),
+                        "mean_work_lup": round(work), **summ,
+                        "capacity_solves_per_s_at_50_Huc": round(cal_lups / work_c4, 4),
+                        "phases_s": {k: round(v, 2) for k, v in srv.phase_s.items()}, "rebatches": srv.rebatches,
+                        "nu_restart_requests": len(gold),
+                        "nu_rel_err_vs_fp64": _nu_errors(res, ref),
+                        "_nu": {r.rid: r.nu for r in res if r.rid in ref}}
     if sequential_fp32:
-        # the plain path: one FP32 lattice at a time, first come first served
-        seq = sorted(reqs, key=lambda r: r.arrival)
+        # the plain path: one FP32 lattice at a time, first come first served,
+        # the last stream's arrivals
         srv1 = S.Server(storage="f32", max_slots=1)
         t0 = time.perf_counter()
-        res1 = srv1.run(seq, realtime=True)
+        res1 = srv1.run(reqs, realtime=True)
         wall1 = time.perf_counter() - t0
-        errs1 = [abs(r.nu - ref[r.rid]) / abs(ref[r.rid]) for r in res1 if r.rid in ref]
+        nu_fp32 = {r.rid: r.nu for r in res1 if r.rid in ref}
         out["single_lattice_fp32"] = {**S.summarize([r for r in res1 if r.rid not in ref], wall1),
-                                      "nu_rel_err_vs_fp64": {"max": max(errs1) if errs1 else None,
-                                                             "n": len(errs1)}}
+                                      "nu_rel_err_vs_fp64": _nu_errors(res1, ref)}
+    for storage in storages:
+        nus = out[storage].pop("_nu")
+        if nu_fp32:
+            e = [abs(nus[k] - nu_fp32[k]) / abs(nu_fp32[k]) for k in nus if k in nu_fp32]
+            out[storage]["nu_rel_err_vs_fp32_same_start"] = {"max": max(e) if e else None, "n": len(e)}
+    out["restart_length"] = "restart requests run 30 H/u_c from the FP64 steady fields"
+    return out
+
+
+def single_extra(torch, tclbm, name, storage, steps, warmup, traffic_json, reduce_every=1000):
+    """A single-lattice figure measured beside the headline: MLUPS over `steps`
+    steps (FP64 sums every `reduce_every`) and the roofline of its kernel."""
+    case, wname = workload_case(name)
+    r = bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, 0, 32)
+    out = {"workload": wname, "storage": storage, "steps": steps,
+           "mlups": round(r["nodes"] * steps / r["wall"] / 1e6, 1),
+           **roofline(bytes_per_lup(storage, case.thermal), r["nodes"], r["avg_launch_s"],
+                      load_traffic(traffic_json, f"{wname}_{storage}"), kernel=r["kernel"])}
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--workload", default="rb", choices=["rb", "shock", "couette", "large", "batch", "serve"])
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="batch", choices=["batch", "rb", "shock", "couette", "large", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f64"])
     ap.add_argument("--reduce-every", type=int, default=1000)
     ap.add_argument("--strip-rows", type=int, default=0)
@@ -365,9 +430,11 @@ def main():
                     help="batch workload: fixed strip height (with --graph-chunk) instead of the autotuner")
     ap.add_argument("--graph-chunk", type=int, default=32)
     ap.add_argument("--requests", type=int, default=500, help="serving stream length")
-    ap.add_argument("--serve-storage", default="f16", choices=["f16", "bf16", "f32"])
+    ap.add_argument("--serve-storage", default="f16,bf16", help="storage forms of the serving streams")
+    ap.add_argument("--time-units", type=float, default=1.0, help="serving request length in flow times")
     ap.add_argument("--no-extras", action="store_true",
-                    help="only the selected workload (no large-lattice roofline, batch or serving figures)")
+                    help="only the selected workload (no other lattices, rooflines or serving figures)")
+    ap.add_argument("--no-serving", action="store_true", help="extras without the serving streams")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the plain HBM copy kernel (2 x 2 GiB) instead and exit")
@@ -387,33 +454,67 @@ def main():
         print(json.dumps(copy_probe(torch, tclbm)), flush=True)
         return
 
+    serve_storages = tuple(x for x in args.serve_storage.split(",") if x)
+
+    if args.workload == "serve":
+        s = bench_serving(torch, tclbm, n_requests=args.requests, storages=serve_storages,
+                          time_units=args.time_units)
+        first = s[serve_storages[0]]
+        out = {"metric": "batched serving solves/s", "value": first["solves_per_s"], "unit": "solves/s",
+               "n_gpus": 1, "steps": first["requests"], "warmup": 0,
+               "ms_per_step": round(1e3 / max(first["solves_per_s"], 1e-9), 3), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
+               "config": {"workload": f"serving stream, {args.requests} requests, {args.time_units} H/u_c",
+                          "storage": serve_storages[0]},
+               "serving": s}
+        print(json.dumps(out), flush=True)
+        return
+
     if args.workload == "batch":
-        log("bench: batched RB workload, 256 instances")
-        b = bench_batch(torch, tclbm, storage=args.storage, steps=min(args.steps, 2000),
-                        warmup=min(args.warmup, 400), strip_rows=args.batch_strip_rows,
+        log(f"bench: batched RB workload, 256 instances, {args.storage}, warmup {args.warmup}, steps {args.steps}")
+        b = bench_batch(torch, tclbm, storage=args.storage, steps=args.steps, warmup=args.warmup,
+                        reduce_every=args.reduce_every, strip_rows=args.batch_strip_rows,
                         graph_chunk=args.graph_chunk if args.batch_strip_rows > 0 else None,
                         traffic_json=args.traffic_json)
-        out = {"metric": "TCLBM MLUPS", "value": b["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": b["steps"],
-               "warmup": b["warmup"], "ms_per_step": b["ms_per_step"], "higher_is_better": True,
-               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
+        out = {"metric": "TCLBM MLUPS", "value": b["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
+               "data": "synthetic (seeded)",
                "config": {"workload": b["workload"], "storage": args.storage, "instances": b["instances"],
-                          "nodes": b["nodes"], "unstable_instances": b["unstable_instances"],
-                          "autotune": b["autotune"]},
+                          "nodes": b["nodes"], "steps_per_reduction": args.reduce_every,
+                          "unstable_instances": b["unstable_instances"],
+                          "redrawn_below_stability_limit": b["redrawn_below_stability_limit"],
+                          "strip_rows": b["strip_rows"], "graph_chunk": b["graph_chunk"],
+                          "device_ms": b["device_ms"], "autotune": b["autotune"]},
                "roofline": b["roofline"]}
+        if not args.no_extras:
+            log("bench: RB 512x256 fp32, 2000 steps")
+            out["rb512x256"] = single_extra(torch, tclbm, "rb", "f32", 2000, 200, args.traffic_json)
+            log("bench: shock tube 8192x4 fp32, 4000 steps")
+            out["shock_tube"] = single_extra(torch, tclbm, "shock", "f32", 4000, 200, args.traffic_json)
+            out["roofline_large"] = {}
+            for st in ("f32", "f16", "bf16"):
+                log(f"bench: RB 8192x4096 {st}, 200 warmup + 1000 timed steps")
+                out["roofline_large"][st] = single_extra(torch, tclbm, "large", st, 1000, 200, args.traffic_json)
+            log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
+            ceil = copy_probe(torch, tclbm)
+            out["hbm_ceiling"] = ceil
+            out["roofline"]["frac_of_ceiling"] = round(out["roofline"]["achieved"] / ceil["GBs"], 4)
+            for st, r in out["roofline_large"].items():
+                r["frac_of_ceiling"] = round(r["achieved"] / ceil["GBs"], 4)
+            if not args.no_serving:
+                log(f"bench: serving streams, {args.requests} requests, {serve_storages}")
+                out["serving"] = bench_serving(torch, tclbm, n_requests=args.requests, storages=serve_storages,
+                                               time_units=args.time_units)
         if not args.no_cpu_baseline:
             from paper_1610_07114_amd import workloads as W
             specs = W.batched_rb_specs(256, seed=0)[:8]
             out["cpu_baseline"] = cpu_baseline([W.rb_from_spec(s) for s in specs],
-                                               label="first 8 lattices of the batched RB workload")
-        print(json.dumps(out), flush=True)
-        return
-
-    if args.workload == "serve":
-        s = bench_serving(torch, tclbm, n_requests=args.requests, storage=args.serve_storage)
-        out = {"metric": "batched serving solves/s", "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-               "steps": s["requests"], "warmup": 0, "ms_per_step": round(1e3 / max(s["solves_per_s"], 1e-9), 3),
-               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-               "data": "synthetic (seeded)", "config": {"workload": "serving stream", **s}}
+                                               label="the first 8 lattices of the batched RB workload "
+                                                     f"({sum(s['nx'] * s['ny'] for s in specs)} nodes)")
+            if not args.no_extras:
+                log("bench: FP64 oracle on one and on all host threads, configs 1-3")
+                out["cpu_baseline_detail"] = cpu_baseline_detail()
         print(json.dumps(out), flush=True)
         return
 
@@ -445,31 +546,8 @@ def main():
     if case.name == "rayleigh_benard":
         m = case.meta
         out["nu"] = 1.0 + r["sums"].nu_num / r["nodes"] * m["H"] / (m["kappa"] * m["dT"])
-
-    if args.workload == "rb" and not args.no_extras:
-        big, bname = workload_case("large")
-        log(f"bench: {bname} f32 roofline, 200 warmup + 1000 timed steps")
-        rl = bench_single(torch, tclbm, big, "f32", 1000, 200, 1000, 0, 32)
-        out["roofline_large"] = {"workload": bname, "mlups": round(rl["nodes"] * 1000 / rl["wall"] / 1e6, 1),
-                                 **roofline(144, rl["nodes"], rl["avg_launch_s"],
-                                            load_traffic(args.traffic_json, f"{bname}_f32"), kernel=rl["kernel"])}
-        del big
-        log("bench: batched RB, 256 instances, f32")
-        out["batch"] = bench_batch(torch, tclbm, storage="f32", traffic_json=args.traffic_json)
-        # the measured ceiling beside the specification: a plain chunked copy
-        log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
-        ceil = copy_probe(torch, tclbm)
-        out["hbm_ceiling"] = ceil
-        out["roofline_large"]["frac_of_ceiling"] = round(out["roofline_large"]["achieved"] / ceil["GBs"], 4)
-        out["batch"]["roofline"]["frac_of_ceiling"] = round(out["batch"]["roofline"]["achieved"] / ceil["GBs"], 4)
-        log(f"bench: serving stream, {args.requests} requests, {args.serve_storage}")
-        out["serving"] = bench_serving(torch, tclbm, n_requests=args.requests, storage=args.serve_storage)
-
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline([case])
-        if args.workload == "rb" and not args.no_extras:
-            log("bench: FP64 oracle on one and on all host threads, configs 1-3")
-            out["cpu_baseline_detail"] = cpu_baseline_detail()
     print(json.dumps(out), flush=True)
 
 

@@ -54,9 +54,15 @@ typedef enum {
  * deviation from a per-row rest-state equilibrium (fixed at create time from
  * the row means of the initial density and temperature), and the arithmetic
  * runs on those deviations.  F16_DEV keeps the deviation times 2^10 as an
- * IEEE half (round to nearest even): deviations from 6.0e-8 up to 64 are
- * normal numbers; a larger one overflows and is reported as unstable.
- * BF16_DEV keeps the deviation as a bfloat16 (round to nearest even). */
+ * IEEE half: deviations from 6.0e-8 up to 64 are normal numbers; a larger one
+ * overflows and is reported as unstable.  BF16_DEV keeps the deviation as a
+ * bfloat16.  Both 16-bit forms round stochastically and without bias: random
+ * bits below the target's last place are added to the FP32 value, which is
+ * then truncated.  The bits come from a counter-based generator keyed by
+ * (lattice step, node, population), so results are deterministic and do not
+ * depend on the launch shape or on the other members of a batch.  (Rounding
+ * to nearest would freeze a stored value whose change per step is below half
+ * a unit in the last place.) */
 typedef enum {
   TCLBM_STORE_F32 = 0,
   TCLBM_STORE_F16_DEV = 1,
@@ -152,14 +158,36 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
                           const double *ax_field, const double *ay_field, tclbm_handle *out);
 
 /* Change the boundary kind of one side and, for WALL, its velocity and
- * temperature, from the next step on (the state is left as it is).
- * E_INVALID for WALL on an x side; an unpaired periodic axis is refused at
- * step time (set both sides of an axis before stepping). */
+ * temperature, from the next step on (the state is left as it is).  The kinds
+ * are those of Section 5: periodic sides; node walls whose velocity and
+ * temperature are imposed by non-equilibrium extrapolation of both DFs from
+ * the adjacent fluid node (the wall treatment of Sections 5B and 5D, applied
+ * before the collision of each step); halfway bounce-back ends (the closed
+ * shock tube of Section 5C).  side: tclbm_side; kind: tclbm_bc_kind; ux_w,
+ * uy_w, T_w: the imposed wall velocity and temperature (used by WALL; T_w > 0;
+ * WALL_ADIABATIC takes its temperature from the fluid, BOUNCEBACK and
+ * PERIODIC ignore all three).  E_INVALID for an unknown side or kind, a WALL
+ * kind on an x side, an adiabatic wall with ny < 4 or a non-finite value
+ * (nothing is changed then); an unpaired periodic axis is refused at step
+ * time (set both sides of an axis before stepping).  Does not touch the
+ * device; a batch that holds the handle must be rebuilt. */
 tclbm_status tclbm_set_bc(tclbm_handle h, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w);
 
-/* Enqueue nsteps time steps (asynchronous).  Long runs replay a captured HIP
- * graph of a fixed chunk of steps (not on the NULL stream, which cannot be
- * captured).  E_INVALID for an unpaired periodic axis. */
+/* Enqueue nsteps time steps (asynchronous, on the handle's stream).  One time
+ * step is the update of Sections 2-4 for every node: wall extrapolation
+ * (Sections 5B/5D), the macroscopic variables of Eq. (20) and the temperature
+ * of Section 4, the correction gradients of Section 4, the cascaded relaxation
+ * of Eq. (8) towards the shifted equilibria of Section 4 with the force source
+ * of Section 3, the post-collision raw moments of Eq. (18) mapped back by
+ * Eq. (3), the energy-DF update of Section 4 with its coupling source K, and
+ * pull streaming of both DFs: Eq. (27) for f and the time-discrete energy-DF
+ * equation of Section 4 for h.  The reading of the energy-DF update
+ * (heq_moments, h_collision, h_force) follows the parameters.  Long runs replay
+ * a captured HIP graph of a fixed chunk of steps (not on the NULL stream, which
+ * cannot be captured).  nsteps >= 0.  E_INVALID for a NULL handle, nsteps < 0
+ * or an unpaired periodic axis; E_STATE once the handle has reported an
+ * unstable state; E_DEVICE when a HIP launch fails (the steps enqueued before
+ * the failure are counted by tclbm_steps_done). */
 tclbm_status tclbm_step(tclbm_handle h, int64_t nsteps);
 
 /* As tclbm_step, then synchronise and report the elapsed device time of the
@@ -193,7 +221,10 @@ tclbm_status tclbm_set_tuning(tclbm_handle h, int32_t strip_rows, int32_t graph_
  * handle.  For profilers and reports: it matches the kernel-trace name. */
 const char *tclbm_step_kernel(tclbm_handle h);
 
-/* Release the handle (waits for its stream).  dev_buf is not freed. */
+/* Release the handle (waits for its stream, frees the library's own field
+ * buffer and captured graphs).  No passage of the paper defines it: resource
+ * management only.  dev_buf and the stream are not freed.  E_INVALID for a
+ * NULL handle. */
 tclbm_status tclbm_destroy(tclbm_handle h);
 
 /* Diagnostic: enqueue one plain streaming copy of `bytes` (multiple of 16,

@@ -37,6 +37,7 @@ struct tclbm_ctx {
   int graph_chunk;
   hipGraphExec_t graph;  // replays graph_chunk steps starting from buffer 0
   bool graph_ok;
+  std::vector<double> th_ref;  // theta_r of each row, as the kernels see it
   char err[512];
 };
 
@@ -175,6 +176,21 @@ void decompose(tclbm_ctx *c) {
   if (rows > k.ny) rows = k.ny;
   k.strip_rows = rows;
   k.n_strips = (k.ny + rows - 1) / rows;
+}
+
+// Wall temperatures as deviations from the wall row's reference theta_r (see
+// KParams::wall_dth), formed in double from the references the kernels use.
+void set_wall_dth(tclbm_ctx *c) {
+  KParams &k = c->k;
+  const int ny = k.ny;
+  for (int side = 0; side < 4; ++side) {
+    k.wall_dth[side] = 0.0;
+    if (side < kYlo || c->th_ref.size() != (size_t)ny) continue;
+    const int yw = (side == kYlo) ? 0 : ny - 1, y1 = (side == kYlo) ? 1 : ny - 2, y2 = (side == kYlo) ? 2 : ny - 3;
+    if (k.bc[side] == kWall) k.wall_dth[side] = k.R * k.wall_T[side] - c->th_ref[yw];
+    else if (k.bc[side] == kWallAdiabatic && ny >= 4)
+      k.wall_dth[side] = (4.0 * c->th_ref[y1] - c->th_ref[y2] - 3.0 * c->th_ref[yw]) / 3.0;
+  }
 }
 
 bool bc_pairs_ok(const KParams &k) {
@@ -380,17 +396,21 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
   do {
     // per-row rest-state references of the deviation storage
     hipError_t e;
+    c->th_ref.resize(p->ny);
     if (p->storage == kF64) {
       std::vector<double> ref;
       build_refs<double>(*p, rho, T, ref);
+      for (int y = 0; y < p->ny; ++y) c->th_ref[y] = ref[2 * y + 1];
       e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     } else {
       std::vector<float> ref;
       build_refs<float>(*p, rho, T, ref);
+      for (int y = 0; y < p->ny; ++y) c->th_ref[y] = (double)ref[2 * y + 1];
       e = hipMemcpyAsync(refs, ref.data(), ref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
+    set_wall_dth(c);
     if (e == hipSuccess) e = hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned), c->stream);
     if (e != hipSuccess) { set_err(c, "ref upload: %s", hipGetErrorString(e)); st = TCLBM_E_DEVICE; break; }
     if (p->accel_field) {
@@ -459,6 +479,7 @@ tclbm_status tclbm_set_bc(tclbm_handle c, int32_t side, int32_t kind, double ux_
   c->k.wall_ux[side] = ux_w;
   c->k.wall_uy[side] = uy_w;
   c->k.wall_T[side] = (kind == kWall) ? T_w : c->p.T0;
+  set_wall_dth(c);
   decompose(c);
   drop_graph(c);
   ++c->version;
@@ -688,7 +709,8 @@ static void batch_drop_graph(tclbm_batch *b) {
   b->graph_ok = false;
 }
 
-static tclbm_status batch_launch(tclbm_batch *b, int64_t n) {
+// n plain launches, one step each; *done counts those enqueued
+static tclbm_status batch_launch(tclbm_batch *b, int64_t n, int64_t *done) {
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, b->parity,
                                      b->all_default, b->all_fit, b->stream);
@@ -697,8 +719,56 @@ static tclbm_status batch_launch(tclbm_batch *b, int64_t n) {
       return TCLBM_E_DEVICE;
     }
     b->parity ^= 1;
+    ++*done;
   }
   return TCLBM_OK;
+}
+
+// Enqueue n steps: replays of the captured chunk while at least two chunks
+// remain (after one plain step if the parity is odd), plain launches for the
+// rest.  *done counts the steps actually enqueued, also on a failure.
+static tclbm_status batch_run(tclbm_batch *b, int64_t n, int64_t *done) {
+  const int ch = b->stream ? b->graph_chunk : 0;
+  if (ch >= 2 && n >= 2 * (int64_t)ch) {
+    if (b->parity) {
+      tclbm_status st = batch_launch(b, 1, done);
+      if (st != TCLBM_OK) return st;
+      --n;
+    }
+    if (!b->graph_ok) {
+      // capture records launches without running them: a failed capture
+      // enqueues nothing
+      hipGraph_t g;
+      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      hipError_t le = hipSuccess;
+      for (int s = 0; s < ch && le == hipSuccess && e == hipSuccess; ++s)
+        le = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, s & 1,
+                               b->all_default, b->all_fit, b->stream);
+      hipError_t ee = (e == hipSuccess) ? hipStreamEndCapture(b->stream, &g) : e;
+      if (e != hipSuccess || le != hipSuccess || ee != hipSuccess) {
+        if (e == hipSuccess && ee == hipSuccess) hipGraphDestroy(g);
+        snprintf(b->err, sizeof(b->err), "batch capture failed");
+        return TCLBM_E_DEVICE;
+      }
+      ee = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ee != hipSuccess) {
+        snprintf(b->err, sizeof(b->err), "batch graph instantiation: %s", hipGetErrorString(ee));
+        return TCLBM_E_DEVICE;
+      }
+      b->graph_ok = true;
+    }
+    while (n >= ch) {
+      hipError_t e = hipGraphLaunch(b->graph, b->stream);
+      if (e != hipSuccess) {
+        snprintf(b->err, sizeof(b->err), "batch graph launch: %s", hipGetErrorString(e));
+        return TCLBM_E_DEVICE;
+      }
+      *done += ch;  // an even chunk leaves the parity unchanged
+      n -= ch;
+    }
+  }
+  return batch_launch(b, n, done);
 }
 
 extern "C" {
@@ -759,40 +829,10 @@ tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
       return TCLBM_E_STATE;
     }
   }
-  const int ch = b->stream ? b->graph_chunk : 0;
-  int64_t n = nsteps;
-  tclbm_status st = TCLBM_OK;
-  if (ch >= 2 && n >= 2 * (int64_t)ch) {
-    if (b->parity) {
-      st = batch_launch(b, 1);
-      --n;
-    }
-    if (st == TCLBM_OK && !b->graph_ok) {
-      hipGraph_t g;
-      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-      hipError_t le = hipSuccess;
-      for (int s = 0; s < ch && le == hipSuccess && e == hipSuccess; ++s)
-        le = launch_batch_step(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage, s & 1,
-                               b->all_default, b->all_fit, b->stream);
-      hipError_t ee = (e == hipSuccess) ? hipStreamEndCapture(b->stream, &g) : e;
-      if (e != hipSuccess || le != hipSuccess || ee != hipSuccess) {
-        if (e == hipSuccess && ee == hipSuccess) hipGraphDestroy(g);
-        snprintf(b->err, sizeof(b->err), "batch capture failed");
-        return TCLBM_E_DEVICE;
-      }
-      ee = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
-      if (ee != hipSuccess) return TCLBM_E_DEVICE;
-      b->graph_ok = true;
-    }
-    while (st == TCLBM_OK && n >= ch) {
-      if (hipGraphLaunch(b->graph, b->stream) != hipSuccess) return TCLBM_E_DEVICE;
-      n -= ch;  // an even chunk leaves the parity unchanged
-    }
-  }
-  if (st == TCLBM_OK) st = batch_launch(b, n);
-  // members' bookkeeping: the state now lives in the buffer the parity names
-  const int64_t done = nsteps - (st == TCLBM_OK ? 0 : n);
+  int64_t done = 0;
+  const tclbm_status st = batch_run(b, nsteps, &done);
+  // members' bookkeeping on every exit path: the state now lives in the buffer
+  // the parity names, after the steps actually enqueued
   for (size_t i = 0; i < b->m.size(); ++i) {
     tclbm_handle h = b->m[i];
     h->steps += done;

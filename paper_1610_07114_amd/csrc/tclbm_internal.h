@@ -28,6 +28,12 @@ struct KParams {
   double mu0_RT0, Pr;
   int bc[4];
   double wall_ux[4], wall_uy[4], wall_T[4];
+  // wall temperatures as deviations of theta = R T from the wall row's
+  // reference, formed in double on the host: WALL sides R T_w - theta_r(wall);
+  // WALL_ADIABATIC sides the reference part of (4 theta_1 - theta_2)/3 -
+  // theta_r(wall), (4 theta_r(1) - theta_r(2) - 3 theta_r(wall))/3, with rows
+  // 1 and 2 counted inwards
+  double wall_dth[4];
   double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;
   const void *axf, *ayf;          // per-node acceleration, compute type, pitch layout (nullable)
   // per-row rest-state reference (compute type): rowref[2y] = rho_r,

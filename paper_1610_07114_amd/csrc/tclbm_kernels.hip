@@ -180,6 +180,8 @@ __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   c.inv_tau_hf = (R)k.inv_tau_hf;
   c.two_b = (R)(2.0 / k.b);
   c.inv_RT0 = (R)(1.0 / (k.R * k.T0));
+  c.RT0f = (R)(k.R * k.T0);
+  c.dRT0 = (R)(k.R * k.T0 - (double)c.RT0f);
   c.thermal = (M >= 1) ? 1 : k.thermal;
   c.correction = (M >= 1) ? 1 : k.correction;
   c.heq_mode = (M >= 1) ? 0 : k.heq_mode;
@@ -456,7 +458,8 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
 template <class R, int M = 0>
 __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, int side, const RowRef<R> &qw,
                                           const RowRef<R> &qI, const R *dI, const R *gI, const Macro<R> &mI,
-                                          R axI, R ayI, R axW, R ayW, R thw, R *dw, R *gw) {
+                                          R axI, R ayI, R axW, R ayW, R dthw, R *dw, R *gw) {
+  const R thw = qw.th + dthw;
   const R aI_n = (side == kYlo) ? -ayI : ayI;
   const R aW_n = (side == kYlo) ? -ayW : ayW;
   const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
@@ -474,7 +477,6 @@ __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, 
     const R den = R(1) + un - R(0.5) * aW_n;
     drw = (D - qw.rho * (un - R(0.5) * aW_n)) / den;
   }
-  const R dthw = thw - qw.th;
   R ew[9], ef[9], sw[9], sf[9];
   feq_dev(qw, drw, uwx, uwy, dthw, ew);
   feq_dev(qI, mI.drho, mI.ux, mI.uy, mI.dth, ef);
@@ -505,7 +507,7 @@ __device__ __forceinline__ void finish(const KParams &k, const Consts<R> &c, int
   R ax, ay;
   node_accel<R, M>(k, y, xc, ax, ay);
   s.m = macros(c, s.q, s.f, s.h, ax, ay);
-  R om = R(1) - s.m.th * c.inv_RT0;
+  R om = one_minus_theta(c, s.q.th, s.m.dth);
   s.qx = s.m.ux * om;
   s.qy = s.m.uy * om;
 }
@@ -556,15 +558,17 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   R axI, ayI, axW, ayW;
   node_accel<R, M>(k, yf, col.xc, axI, ayI);
   node_accel<R, M>(k, y, col.xc, axW, ayW);
-  R thw = c.R_ * (flags<M>(k).thermal ? (R)k.wall_T[side] : c.T0);
+  // wall temperature as a deviation from the wall row's reference; the O(1)
+  // parts are formed in double on the host (wall_dth)
+  R dthw = flags<M>(k).thermal ? (R)k.wall_dth[side] : c.R_ * c.T0 - s.q.th;
   if (flags<M>(k).thermal && k.bc[side] == kWallAdiabatic) {
     // zero normal temperature gradient to second order, -3 T_w + 4 T_1 - T_2 = 0,
     // with the row two inside the wall evaluated here (ny >= 4: a fluid row)
     RowState<R> two;
     get_row<S, M>(k, c, (y == 0) ? 2 : y - 2, col, two);
-    thw = (R(4) * in.m.th - two.m.th) * (R(1) / R(3));
+    dthw += (R(4) * in.m.dth - two.m.dth) * (R(1) / R(3));
   }
-  wall_node<R, M>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, thw, s.f, s.h);
+  wall_node<R, M>(k, c, side, s.q, in.q, in.f, in.h, in.m, axI, ayI, axW, ayW, dthw, s.f, s.h);
   finish<R, M>(k, c, y, col.xc, s);
 }
 
@@ -1112,9 +1116,13 @@ __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho,
     }
     const long long j = (long long)ty * k.nx + tx;
     const RowRef<R> q = row_ref(k, c, ty);
-    const R r = (R)rho[j], vx = (R)ux[j], vy = (R)uy[j];
-    const R th = c.R_ * (k.thermal ? (R)T[j] : c.T0);
-    const R drho = r - q.rho, dth = th - q.th;
+    // deviations from the row reference formed in double from the double
+    // inputs: the O(1) density and temperature are never rounded to the
+    // compute type before the subtraction
+    const R drho = (R)(rho[j] - (double)q.rho);
+    const R dth = (R)(k.R * (k.thermal ? T[j] : k.T0) - (double)q.th);
+    const R r = q.rho + drho, th = q.th + dth;
+    const R vx = (R)ux[j], vy = (R)uy[j];
     R ax, ay;
     node_accel<R>(k, ty, tx, ax, ay);
     R fe[9], se[9], he[9];

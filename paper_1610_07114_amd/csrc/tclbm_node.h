@@ -127,7 +127,19 @@ struct Consts {
   R R_, T0, b, w1, w2, w3, w4, wh, inv_tau_hf;
   int thermal, correction, heq_mode, h_coll, h_force;
   R two_b, inv_RT0;  // 2/b and 1/(R T0)
+  // R T0 in the compute type and its rounding error, R T0 - RT0f (formed in
+  // double): theta - R T0 = ((theta_r - RT0f) + dRT0) + dtheta, where the
+  // first difference is exact (both near 1/3)
+  R RT0f, dRT0;
 };
+
+// 1 - theta/theta0 of a node from its row reference and deviation, without
+// rounding the O(1) temperature itself (the correction term's
+// u(1 - theta) is a small difference)
+template <class R>
+TC_HD R one_minus_theta(const Consts<R> &c, R th_ref, R dth) {
+  return -(((th_ref - c.RT0f) + c.dRT0) + dth) * c.inv_RT0;
+}
 
 // 1/x: IEEE division in FP64; in FP32 on the GPU the hardware reciprocal
 // refined by one Newton step (within an ulp or so, no division sequence).

@@ -41,10 +41,17 @@ class Request:
     steps: int
     arrival: float     # seconds after the start of the run
     seed: int
+    # restart: initial rho, ux, uy, T ([ny, nx] float64) in place of the
+    # seeded conduction state (RB only)
+    init: Optional[dict] = field(default=None, repr=False)
 
     def case(self) -> W.Case:
         if self.kind == "rb":
-            return W.rayleigh_benard(nx=self.nx, ny=self.ny, Ra=self.Ra, Pr=self.Pr, seed=self.seed)
+            c = W.rayleigh_benard(nx=self.nx, ny=self.ny, Ra=self.Ra, Pr=self.Pr, seed=self.seed)
+            if self.init is not None:
+                c = c.with_(**{k: np.ascontiguousarray(self.init[k], dtype=np.float64)
+                               for k in ("rho", "ux", "uy", "T")})
+            return c
         # w2 = w3 = w4 = 1 as in the paper's other thermal cases: its Couette
         # set (1.1, 1.6, 0.3) is unstable to 2-D perturbations, which a
         # Couette lattice wider than it is periodic only escapes while it
@@ -60,9 +67,12 @@ def solve_steps(kind: str, ny: int, time_units: float) -> int:
 
 
 def make_requests(n: int, rate: float, seed: int = 0, nmin: int = 32, nmax: int = 1024, rb_frac: float = 0.8,
-                  time_units: float = 1.0, Ra_range=(1e4, 1e6), Pr_range=(0.5, 7.0)) -> List[Request]:
+                  time_units: float = 1.0, Ra_range=(1e4, 1e6), Pr_range=(0.5, 7.0),
+                  tau_min: float = W.TAU_STABLE) -> List[Request]:
     """Seeded Poisson arrivals (rate per second) of 2N x N solves, N log-uniform
-    on [nmin, nmax], Ra log-uniform, Pr uniform, 80% RB / 20% Couette."""
+    on [nmin, nmax], Ra log-uniform, Pr uniform, 80% RB / 20% Couette.  As in
+    the batched workload, an RB draw whose 1/w1 falls below `tau_min` (the
+    scheme's linear stability limit) is drawn again."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -72,8 +82,22 @@ def make_requests(n: int, rate: float, seed: int = 0, nmin: int = 32, nmax: int 
         kind = "rb" if rng.uniform() < rb_frac else "couette"
         Ra = math.exp(rng.uniform(math.log(Ra_range[0]), math.log(Ra_range[1])))
         Pr = float(rng.uniform(*Pr_range))
+        if kind == "rb" and W.rb_tau_f(N, Ra, Pr) < tau_min:
+            # redraws come from a generator of their own (keyed by the stream
+            # seed and the request index), so arrivals, kinds and the other
+            # requests do not depend on them
+            r2 = np.random.default_rng([seed, i])
+            while W.rb_tau_f(N, Ra, Pr) < tau_min:
+                N = int(round(math.exp(r2.uniform(math.log(nmin), math.log(nmax)))))
+                Ra = math.exp(r2.uniform(math.log(Ra_range[0]), math.log(Ra_range[1])))
+                Pr = float(r2.uniform(*Pr_range))
         out.append(Request(i, kind, 2 * N, N, Ra, Pr, solve_steps(kind, N, time_units), t, seed * 100003 + i))
     return out
+
+
+def mean_work(requests: Sequence[Request]) -> float:
+    """Mean lattice updates per request (nodes x steps)."""
+    return sum(r.nx * r.ny * r.steps for r in requests) / max(1, len(requests))
 
 
 def nusselt_from_sums(case: W.Case, sums) -> float:

@@ -249,18 +249,38 @@ def uniform_noise(nx: int, ny: int, seed: int = 0, amp_rho: float = 0.05, amp_u:
 
 
 # --------------------------------------------------------------------------------
+# Below this 1/w1 the default thermal scheme is linearly unstable (spectral
+# radius of the linearised step above 1): such lattices blow up whatever the
+# arithmetic precision.
+TAU_STABLE = 0.55
+
+
+def rb_tau_f(N: int, Ra: float, Pr: float) -> float:
+    """1/w1 of a 2N x N Rayleigh-Benard instance (rb_parameters' viscosity)."""
+    return rb_parameters(N, Ra, Pr)["tau_f"]
+
+
 def batched_rb_specs(n: int = 256, seed: int = 0, nmin: int = 32, nmax: int = 512, Ra_range=(1e4, 1e6),
-                     Pr_range=(0.5, 7.0)) -> List[dict]:
+                     Pr_range=(0.5, 7.0), tau_min: float = TAU_STABLE, rejected: Optional[list] = None) -> List[dict]:
     """Seeded instance list of the batched Rayleigh-Benard workload: N log-uniform
     on [nmin, nmax] (lattice 2N x N), Ra log-uniform, Pr uniform; per-instance
-    noise seed = seed + i."""
+    noise seed = seed + i.  Draws whose 1/w1 falls below `tau_min` (small
+    lattices at high Ra and low Pr: too little viscosity for the scheme's
+    stability limit) are skipped, so the list holds n instances of the same
+    distribution conditioned on linear stability; `rejected` (a list), when
+    given, receives the skipped draws.  tau_min = 0 keeps every draw."""
     rng = np.random.default_rng(seed)
     out = []
-    for i in range(n):
+    while len(out) < n:
         N = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
         Ra = math.exp(rng.uniform(math.log(Ra_range[0]), math.log(Ra_range[1])))
         Pr = rng.uniform(*Pr_range)
-        out.append(dict(nx=2 * N, ny=N, Ra=Ra, Pr=Pr, seed=seed + i))
+        spec = dict(nx=2 * N, ny=N, Ra=Ra, Pr=Pr, seed=seed + len(out))
+        if rb_tau_f(N, Ra, Pr) < tau_min:
+            if rejected is not None:
+                rejected.append(spec)
+            continue
+        out.append(spec)
     return out
 
 

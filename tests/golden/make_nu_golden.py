@@ -107,7 +107,9 @@ def run_history(args):
 
 
 def batch_subset(count: int = 30, nmax: int = 64):
-    specs = W.batched_rb_specs(BATCH_N, seed=BATCH_SEED)
+    # the stored subset indexes the unconditioned draw sequence (every draw
+    # kept), filtered here by its own 1/w1 floor
+    specs = W.batched_rb_specs(BATCH_N, seed=BATCH_SEED, tau_min=0.0)
     picked = []
     for i, s in enumerate(specs):
         c = W.rb_from_spec(s)

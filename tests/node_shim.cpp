@@ -6,7 +6,8 @@ using namespace tclbm;
 
 static Consts<double> consts(const double *c) {
   return Consts<double>{c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], c[8],
-                        (int)c[9], (int)c[10], (int)c[11], (int)c[12], (int)c[13], 2.0 / c[2], 1.0 / (c[0] * c[1])};
+                        (int)c[9], (int)c[10], (int)c[11], (int)c[12], (int)c[13], 2.0 / c[2], 1.0 / (c[0] * c[1]),
+                        c[0] * c[1], 0.0};
 }
 
 extern "C" {

@@ -16,8 +16,9 @@ def S():
 
 
 def test_request_stream_is_seeded_and_shaped(S):
-    a = S.make_requests(2000, rate=50.0, seed=11)
-    b = S.make_requests(2000, rate=50.0, seed=11)
+    # the unconditioned draws (every RB draw kept) carry the stated distributions
+    a = S.make_requests(2000, rate=50.0, seed=11, tau_min=0.0)
+    b = S.make_requests(2000, rate=50.0, seed=11, tau_min=0.0)
     assert [(r.nx, r.ny, r.kind, r.Ra, r.Pr, r.arrival) for r in a] == \
            [(r.nx, r.ny, r.kind, r.Ra, r.Pr, r.arrival) for r in b]
     N = np.array([r.ny for r in a])
@@ -34,6 +35,30 @@ def test_request_stream_is_seeded_and_shaped(S):
     assert Pr.min() >= 0.5 and Pr.max() <= 7.0
     Ra = np.array([r.Ra for r in a])
     assert Ra.min() >= 1e4 and Ra.max() <= 1e6
+
+
+def test_rb_requests_are_above_the_stability_limit(S):
+    """By default an RB draw below 1/w1 = 0.55 is drawn again; Couette
+    requests are untouched (1/w1 = 0.65)."""
+    a = S.make_requests(2000, rate=50.0, seed=11)
+    raw = S.make_requests(2000, rate=50.0, seed=11, tau_min=0.0)
+    assert min(W.rb_tau_f(r.ny, r.Ra, r.Pr) for r in a if r.kind == "rb") >= W.TAU_STABLE
+    assert any(W.rb_tau_f(r.ny, r.Ra, r.Pr) < W.TAU_STABLE for r in raw if r.kind == "rb")
+    # arrivals and kinds do not depend on the redraws
+    assert [(r.arrival, r.kind) for r in a] == [(r.arrival, r.kind) for r in raw]
+    assert all((x.ny, x.Ra, x.Pr) == (y.ny, y.Ra, y.Pr) for x, y in zip(a, raw)
+               if x.kind == "couette" or W.rb_tau_f(y.ny, y.Ra, y.Pr) >= W.TAU_STABLE)
+
+
+def test_restart_request_uses_its_fields(S):
+    ny, nx = 6, 12
+    f = {"rho": np.full((ny, nx), 1.01), "ux": np.full((ny, nx), 0.002), "uy": np.zeros((ny, nx)),
+         "T": np.full((ny, nx), 1.003)}
+    q = S.Request(0, "rb", nx, ny, 2e4, 0.71, 10, 0.0, 3, init=f)
+    c = q.case()
+    for k in ("rho", "ux", "uy", "T"):
+        assert np.array_equal(getattr(c, k), f[k])
+    assert c.meta["Ra"] == 2e4 and c.bc == (W.PERIODIC, W.PERIODIC, W.WALL, W.WALL)
 
 
 def test_run_length_follows_time_scale(S):
@@ -65,12 +90,27 @@ def test_summary(S):
 
 
 def test_batched_specs_shape():
-    specs = W.batched_rb_specs(256, seed=0)
-    assert specs == W.batched_rb_specs(256, seed=0)
-    N = np.array([s["ny"] for s in specs])
+    raw = W.batched_rb_specs(256, seed=0, tau_min=0.0)
+    assert raw == W.batched_rb_specs(256, seed=0, tau_min=0.0)
+    N = np.array([s["ny"] for s in raw])
     assert N.min() >= 32 and N.max() <= 512
-    assert all(s["nx"] == 2 * s["ny"] for s in specs)
-    assert [s["seed"] for s in specs] == list(range(256))
-    nodes = sum(s["nx"] * s["ny"] for s in specs)
+    assert all(s["nx"] == 2 * s["ny"] for s in raw)
+    assert [s["seed"] for s in raw] == list(range(256))
+    nodes = sum(s["nx"] * s["ny"] for s in raw)
     # E[2N^2] for N log-uniform on [32, 512] is about 94,000 nodes per lattice
     assert 0.7 * 256 * 94180 < nodes < 1.3 * 256 * 94180
+
+
+def test_batched_specs_are_conditioned_on_stability():
+    """The default list is the draw sequence with the draws below the scheme's
+    linear stability limit (1/w1 < 0.55) left out and 256 kept."""
+    rejected = []
+    specs = W.batched_rb_specs(256, seed=0, rejected=rejected)
+    assert len(specs) == 256 and len(rejected) > 0
+    assert all(W.rb_tau_f(s["ny"], s["Ra"], s["Pr"]) >= W.TAU_STABLE for s in specs)
+    assert all(W.rb_tau_f(s["ny"], s["Ra"], s["Pr"]) < W.TAU_STABLE for s in rejected)
+    long_raw = W.batched_rb_specs(256 + len(rejected), seed=0, tau_min=0.0)
+    key = lambda s: (s["nx"], s["ny"], s["Ra"], s["Pr"])
+    assert [key(s) for s in long_raw if W.rb_tau_f(s["ny"], s["Ra"], s["Pr"]) >= W.TAU_STABLE] == \
+           [key(s) for s in specs]
+    assert [s["seed"] for s in specs] == list(range(256))
