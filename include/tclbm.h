@@ -200,6 +200,23 @@ tclbm_status tclbm_step_timed(tclbm_handle h, int64_t nsteps, double *ms);
  * T <= 0; the handle then refuses further steps with E_STATE. */
 tclbm_status tclbm_moments(tclbm_handle h, double *rho, double *ux, double *uy, double *T, tclbm_sums *sums);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as tclbm_moments, bitwise, without any allocation.  The per-block
+ * FP64 partial sums and the staged fields go through a fixed device array of
+ * 4 MiB that the library holds on every GPU it runs on until the process ends
+ * (not through the handle's buffers); the lattice is reduced in chunks of at
+ * most 512 blocks of 256 nodes, in the block order of tclbm_moments, so any
+ * lattice size is accepted.  Works on the handle's device (made current for
+ * the call).  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other host threads, other handles) race and must be serialised by
+ * the caller.  Nothing in the array has to start at zero: each chunk rewrites
+ * what it reads.  Host outputs as in tclbm_moments (any pointer may be NULL);
+ * synchronises the handle's stream once per chunk.  Status codes as
+ * tclbm_moments, plus E_DEVICE when the array's address cannot be obtained. */
+tclbm_status tclbm_moments_noalloc(tclbm_handle h, double *rho, double *ux, double *uy, double *T,
+                                   tclbm_sums *sums);
+
 /* Number of time steps taken so far. */
 int64_t tclbm_steps_done(tclbm_handle h);
 

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,7 @@ struct tclbm_ctx {
   hipGraphExec_t graph;  // replays graph_chunk steps starting from buffer 0
   bool graph_ok;
   std::vector<double> th_ref;  // theta_r of each row, as the kernels see it
+  int dev;                     // device current at create
   char err[512];
 };
 
@@ -320,6 +322,42 @@ tclbm_status do_steps(tclbm_ctx *c, int64_t n) {
   return launch_steps(c, n);
 }
 
+// FP64 sums: block partials added in block order (deterministic), then the
+// instability check shared by both moments entry points.
+void sums_begin(tclbm_sums &s, double &bad) {
+  memset(&s, 0, sizeof(s));
+  s.rho_min = 1e300;
+  s.T_min = 1e300;
+  bad = 0;
+}
+
+void sums_add(tclbm_sums &s, double &bad, const double *part, int nblocks) {
+  for (int b = 0; b < nblocks; ++b) {
+    const double *v = &part[(size_t)b * kNumSums];
+    s.mass += v[kSumMass];
+    s.momx += v[kSumMx];
+    s.momy += v[kSumMy];
+    s.energy += v[kSumE];
+    s.kinetic += v[kSumKin];
+    s.nu_num += v[kSumNu];
+    s.rho_min = std::fmin(s.rho_min, v[kSumRhoMin]);
+    s.T_min = std::fmin(s.T_min, v[kSumTMin]);
+    bad += v[kSumBad];
+  }
+}
+
+tclbm_status sums_end(tclbm_ctx *c, tclbm_sums &s, double bad, tclbm_sums *out) {
+  s.nonfinite = (int64_t)bad;
+  if (out) *out = s;
+  if (s.nonfinite > 0 || !(s.rho_min > 0) || !(s.T_min > 0)) {
+    c->unstable = true;
+    set_err(c, "unstable state: %lld non-finite nodes, rho_min %g, T_min %g", (long long)s.nonfinite, s.rho_min,
+            s.T_min);
+    return TCLBM_E_UNSTABLE;
+  }
+  return TCLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -370,6 +408,10 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
 
   tclbm_ctx *c = new (std::nothrow) tclbm_ctx();
   if (!c) return TCLBM_E_NOMEM;
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return TCLBM_E_DEVICE;
+  }
   c->p = *p;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->base = reinterpret_cast<char *>(dev_buf);
@@ -554,31 +596,99 @@ tclbm_status tclbm_moments(tclbm_handle c, double *rho, double *ux, double *uy, 
       HIP_TRY(c, hipMemcpyAsync(outs[q], F + (size_t)q * n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   tclbm_sums s;
-  memset(&s, 0, sizeof(s));
-  s.rho_min = 1e300;
-  s.T_min = 1e300;
-  double bad = 0;
-  for (int b = 0; b < nb; ++b) {  // fixed order: deterministic
-    const double *v = &part[(size_t)b * kNumSums];
-    s.mass += v[kSumMass];
-    s.momx += v[kSumMx];
-    s.momy += v[kSumMy];
-    s.energy += v[kSumE];
-    s.kinetic += v[kSumKin];
-    s.nu_num += v[kSumNu];
-    s.rho_min = std::fmin(s.rho_min, v[kSumRhoMin]);
-    s.T_min = std::fmin(s.T_min, v[kSumTMin]);
-    bad += v[kSumBad];
+  double bad;
+  sums_begin(s, bad);
+  sums_add(s, bad, part.data(), nb);
+  return sums_end(c, s, bad, sums);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------- moments without allocation ---
+// Device scratch of tclbm_moments_noalloc: a file-scope array, so every GPU the
+// library runs on holds its own copy (at its own address) until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device memory:
+// host code uses only the address hipGetSymbolAddress returns for each device.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static unsigned char *g_scratch[kMaxDevices];  // per device, set once
+static std::mutex g_scratch_mu;
+// block partials of one chunk, copied to the caller's thread stack
+constexpr int kChunkBlocks = 512;
+
+// Address of the scratch array on device `dev`, which must be current.
+static tclbm_status scratch_on(tclbm_ctx *c, int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_err(c, "device %d beyond the %d the scratch table holds", dev, kMaxDevices);
+    return TCLBM_E_DEVICE;
   }
-  s.nonfinite = (int64_t)bad;
-  if (sums) *sums = s;
-  if (s.nonfinite > 0 || !(s.rho_min > 0) || !(s.T_min > 0)) {
-    c->unstable = true;
-    set_err(c, "unstable state: %lld non-finite nodes, rho_min %g, T_min %g", (long long)s.nonfinite, s.rho_min,
-            s.T_min);
-    return TCLBM_E_UNSTABLE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_err(c, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      return TCLBM_E_DEVICE;
+    }
+    g_scratch[dev] = reinterpret_cast<unsigned char *>(p);
   }
+  *out = g_scratch[dev];
   return TCLBM_OK;
+}
+
+static tclbm_status moments_noalloc(tclbm_ctx *c, double *rho, double *ux, double *uy, double *T, tclbm_sums *sums) {
+  unsigned char *base = nullptr;
+  tclbm_status st = scratch_on(c, c->dev, &base);
+  if (st != TCLBM_OK) return st;
+  const long long n = (long long)c->p.nx * c->p.ny;
+  const int bn = moments_block_nodes();
+  const long long nb = (n + bn - 1) / bn;
+  double *outs[4] = {rho, ux, uy, T};
+  const bool want = rho || ux || uy || T;
+  // per chunk: partials of its blocks, then (when fields are asked for) the
+  // four fields of its nodes; both rewritten in full by every chunk
+  const size_t per_block = sizeof(double) * (kNumSums + (want ? 4 * (size_t)bn : 0));
+  const int chunk = (int)std::min<size_t>(kChunkBlocks, kScratchBytes / per_block);
+  double *d_part = reinterpret_cast<double *>(base);
+  double *d_f = d_part + (size_t)chunk * kNumSums;
+  const size_t fstride = (size_t)chunk * bn;
+  double part[kChunkBlocks * kNumSums];
+  KParams k = c->k;
+  k.src = c->buf[c->cur];
+  tclbm_sums s;
+  double bad;
+  sums_begin(s, bad);
+  for (long long b0 = 0; b0 < nb; b0 += chunk) {
+    const int m = (int)std::min<long long>(chunk, nb - b0);
+    const long long i0 = b0 * bn, cnt = std::min<long long>((long long)m * bn, n - i0);
+    HIP_TRY(c, launch_moments_range(k, c->p.storage, b0, m, want ? d_f : nullptr, want ? d_f + fstride : nullptr,
+                                    want ? d_f + 2 * fstride : nullptr, want ? d_f + 3 * fstride : nullptr, d_part,
+                                    c->stream));
+    HIP_TRY(c, hipMemcpyAsync(part, d_part, sizeof(double) * kNumSums * m, hipMemcpyDeviceToHost, c->stream));
+    for (int q = 0; q < 4; ++q)
+      if (outs[q])
+        HIP_TRY(c, hipMemcpyAsync(outs[q] + i0, d_f + q * fstride, sizeof(double) * cnt, hipMemcpyDeviceToHost,
+                                  c->stream));
+    // the next chunk reuses the scratch and `part`
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    sums_add(s, bad, part, m);
+  }
+  return sums_end(c, s, bad, sums);
+}
+
+extern "C" {
+
+tclbm_status tclbm_moments_noalloc(tclbm_handle c, double *rho, double *ux, double *uy, double *T,
+                                   tclbm_sums *sums) {
+  if (!c) return TCLBM_E_INVALID;
+  if (!bc_pairs_ok(c->k)) return TCLBM_E_INVALID;
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return TCLBM_E_DEVICE;
+  if (prev != c->dev && hipSetDevice(c->dev) != hipSuccess) return TCLBM_E_DEVICE;
+  const tclbm_status st = moments_noalloc(c, rho, ux, uy, T, sums);
+  if (prev != c->dev) (void)hipSetDevice(prev);
+  return st;
 }
 
 int64_t tclbm_steps_done(tclbm_handle c) { return c ? c->steps : -1; }

@@ -82,6 +82,11 @@ hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const
 hipError_t launch_moments(const KParams &k, int storage, double *d_rho, double *d_ux, double *d_uy,
                           double *d_T, double *d_partials, int *nblocks_out, hipStream_t s);
 int moments_blocks(const KParams &k);
+int moments_block_nodes();  // nodes per moments block
+// blocks [block0, block0 + nblocks) of launch_moments; fields written from the
+// block's first node on (at index 0 for block0), partials at 0 for block0
+hipError_t launch_moments_range(const KParams &k, int storage, long long block0, int nblocks, double *d_rho,
+                                double *d_ux, double *d_uy, double *d_T, double *d_partials, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipStream_t s);
 

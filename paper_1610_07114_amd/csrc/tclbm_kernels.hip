@@ -1165,13 +1165,17 @@ hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const
 // calls give bitwise-identical sums).
 constexpr int kMomThreads = 256;
 
+// Nodes i0 + [0, gridDim.x * kMomThreads) (i0 a multiple of kMomThreads, so
+// that the blocks and their sums are those of a launch over the whole
+// lattice); fields are written at i - i0, partials at the block index.
 template <int S>
-__global__ __launch_bounds__(kMomThreads) void moments_kernel(KParams k, double *frho, double *fux, double *fuy,
-                                                              double *fT, double *partials) {
+__global__ __launch_bounds__(kMomThreads) void moments_kernel(KParams k, long long i0, double *frho, double *fux,
+                                                              double *fuy, double *fT, double *partials) {
   using R = typename Real<S>::T;
   __shared__ double red[kNumSums][kMomThreads];
   const long long n = (long long)k.nx * k.ny;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = i0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long o = i - i0;
   const Consts<R> c = make_consts<R>(k);
   double v[kNumSums];
 #pragma unroll
@@ -1192,10 +1196,10 @@ __global__ __launch_bounds__(kMomThreads) void moments_kernel(KParams k, double 
     const double r = (double)s.q.rho + (double)s.m.drho, u = (double)s.m.ux, w = (double)s.m.uy;
     const double tmt0 = ((double)s.q.th - k.R * k.T0 + (double)s.m.dth) / k.R;  // T - T0
     const double t = k.T0 + tmt0;
-    if (frho) frho[i] = r;
-    if (fux) fux[i] = u;
-    if (fuy) fuy[i] = w;
-    if (fT) fT[i] = t;
+    if (frho) frho[o] = r;
+    if (fux) fux[o] = u;
+    if (fuy) fuy[o] = w;
+    if (fT) fT[o] = t;
     const double hs = k.thermal ? (double)s.q.rho * (double)s.q.E + (double)s.m.sg : 0.0;
     const bool bad = !(isfinite(r) && isfinite(u) && isfinite(w) && isfinite(t));
     v[kSumMass] = r;
@@ -1233,23 +1237,32 @@ int moments_blocks(const KParams &k) {
   return (int)((n + kMomThreads - 1) / kMomThreads);
 }
 
+int moments_block_nodes() { return kMomThreads; }
+
 hipError_t launch_moments(const KParams &k, int storage, double *d_rho, double *d_ux, double *d_uy, double *d_T,
                           double *d_partials, int *nblocks_out, hipStream_t s) {
   const int nb = moments_blocks(k);
   if (nblocks_out) *nblocks_out = nb;
-  dim3 grid(nb), block(kMomThreads);
+  return launch_moments_range(k, storage, 0, nb, d_rho, d_ux, d_uy, d_T, d_partials, s);
+}
+
+hipError_t launch_moments_range(const KParams &k, int storage, long long block0, int nblocks, double *d_rho,
+                                double *d_ux, double *d_uy, double *d_T, double *d_partials, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  const long long i0 = block0 * kMomThreads;
+  dim3 grid(nblocks), block(kMomThreads);
   switch (storage) {
     case kF32:
-      hipLaunchKernelGGL(moments_kernel<kF32>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      hipLaunchKernelGGL(moments_kernel<kF32>, grid, block, 0, s, k, i0, d_rho, d_ux, d_uy, d_T, d_partials);
       break;
     case kF16:
-      hipLaunchKernelGGL(moments_kernel<kF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      hipLaunchKernelGGL(moments_kernel<kF16>, grid, block, 0, s, k, i0, d_rho, d_ux, d_uy, d_T, d_partials);
       break;
     case kBF16:
-      hipLaunchKernelGGL(moments_kernel<kBF16>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      hipLaunchKernelGGL(moments_kernel<kBF16>, grid, block, 0, s, k, i0, d_rho, d_ux, d_uy, d_T, d_partials);
       break;
     case kF64:
-      hipLaunchKernelGGL(moments_kernel<kF64>, grid, block, 0, s, k, d_rho, d_ux, d_uy, d_T, d_partials);
+      hipLaunchKernelGGL(moments_kernel<kF64>, grid, block, 0, s, k, i0, d_rho, d_ux, d_uy, d_T, d_partials);
       break;
     default: return hipErrorInvalidValue;
   }

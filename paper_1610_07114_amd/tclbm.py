@@ -52,7 +52,7 @@ class tclbm_sums(ctypes.Structure):
 
 
 EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_set_bc", "tclbm_step",
-           "tclbm_step_timed", "tclbm_moments", "tclbm_steps_done", "tclbm_read_state", "tclbm_set_tuning",
+           "tclbm_step_timed", "tclbm_moments", "tclbm_moments_noalloc", "tclbm_steps_done", "tclbm_read_state", "tclbm_set_tuning",
            "tclbm_step_kernel", "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
            "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
            "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_set_strip_rows",
@@ -85,6 +85,8 @@ def _load():
     lib.tclbm_step_timed.restype = ctypes.c_int
     lib.tclbm_moments.argtypes = [H, d, d, d, d, ctypes.POINTER(tclbm_sums)]
     lib.tclbm_moments.restype = ctypes.c_int
+    lib.tclbm_moments_noalloc.argtypes = [H, d, d, d, d, ctypes.POINTER(tclbm_sums)]
+    lib.tclbm_moments_noalloc.restype = ctypes.c_int
     lib.tclbm_steps_done.argtypes = [H]
     lib.tclbm_steps_done.restype = ctypes.c_int64
     lib.tclbm_step_kernel.argtypes = [H]
@@ -183,6 +185,16 @@ def tclbm_moments(h, nx: int, ny: int, fields: bool = True, check: bool = True):
     out = [np.empty(nx * ny) for _ in range(4)] if fields else [None] * 4
     s = tclbm_sums()
     st = _lib.tclbm_moments(h, *[_dp(o) for o in out], ctypes.byref(s))
+    if check:
+        _chk(st, h)
+    res = [None if o is None else o.reshape(ny, nx) for o in out]
+    return (*res, s, st)
+
+
+def tclbm_moments_noalloc(h, nx: int, ny: int, fields: bool = True, check: bool = True):
+    out = [np.empty(nx * ny) for _ in range(4)] if fields else [None] * 4
+    s = tclbm_sums()
+    st = _lib.tclbm_moments_noalloc(h, *[_dp(o) for o in out], ctypes.byref(s))
     if check:
         _chk(st, h)
     res = [None if o is None else o.reshape(ny, nx) for o in out]
