@@ -285,6 +285,7 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
     wall = time.perf_counter() - t0
     dev_ms = ev0.elapsed_time(ev1)
     waves = b.waves
+    kernel = b.kernel
     b.close()
     unstable = 0
     for lat in lats:
@@ -300,7 +301,7 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
             "redrawn_below_stability_limit": len(rejected), "strip_rows": rows_in_use,
             "roofline": roofline(bpl, nodes, dev_ms / 1e3 / steps,
                                  load_traffic(traffic_json, f"batched_rayleigh_benard_{n}_{storage}_rows{rows_in_use}")
-                                 if traffic_json else None, kernel="batch_step_kernel")}
+                                 if traffic_json else None, kernel=kernel)}
 
 
 # ------------------------------------------------------------------ serving ---

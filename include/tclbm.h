@@ -275,6 +275,10 @@ tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk);
  * height.  Synchronizes the stream.  Returns TCLBM_E_INVALID for rows < 0. */
 tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows);
 int32_t tclbm_batch_strip_rows(tclbm_batch_handle b);  /* height in use */
+/* Name of the kernel a batch step launches ("batch_step_kernel_f32",
+ * "batch_step_kernel" for 16-bit storage, "batch_step_kernel_f64"), as a
+ * kernel trace shows it; a static string, NULL for a NULL batch. */
+const char *tclbm_batch_step_kernel(tclbm_batch_handle b);
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b);
 
 /* Static string for a status code; last HIP/validation message of a handle. */

@@ -193,6 +193,7 @@ void set_wall_dth(tclbm_ctx *c) {
     else if (k.bc[side] == kWallAdiabatic && ny >= 4)
       k.wall_dth[side] = (4.0 * c->th_ref[y1] - c->th_ref[y2] - 3.0 * c->th_ref[yw]) / 3.0;
   }
+  fill_f32_consts(k);
 }
 
 bool bc_pairs_ok(const KParams &k) {
@@ -996,6 +997,8 @@ tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows) {
 }
 
 int32_t tclbm_batch_strip_rows(tclbm_batch_handle b) { return b ? b->strip_rows : -1; }
+
+const char *tclbm_batch_step_kernel(tclbm_batch_handle b) { return b ? batch_step_kernel_name(b->storage) : nullptr; }
 
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b) {
   if (!b) return TCLBM_E_INVALID;

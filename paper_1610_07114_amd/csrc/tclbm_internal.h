@@ -35,6 +35,13 @@ struct KParams {
   // 1 and 2 counted inwards
   double wall_dth[4];
   double R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, ax, ay;
+  // the constants in FP32, rounded once on the host (the FP32 kernels would
+  // otherwise convert the doubles with vector instructions wherever the
+  // compiler reloads them)
+  struct F32 {
+    float R, T0, b, w1, w2, w3, w4, wh, inv_tau_hf, two_b, inv_RT0, RT0f, dRT0, ax, ay;
+    float wall_ux[4], wall_uy[4], wall_dth[4];
+  } f32;
   const void *axf, *ayf;          // per-node acceleration, compute type, pitch layout (nullable)
   // per-row rest-state reference (compute type): rowref[2y] = rho_r,
   // rowref[2y+1] = theta_r = R T_r; shiftF/H[9y + a] = r_a(row y - e_ay) - r_a(y)
@@ -58,11 +65,38 @@ __host__ __device__ inline bool default_scheme(const KParams &k) {
          k.wall_rho == 0 && k.axf == nullptr && k.visc_mode == 0;
 }
 
-// Buffer-resource addressing of the default scheme (16-bit storage): one
-// descriptor per state buffer, so its 18 planes must span less than 4 GiB.
+// Buffer-resource addressing of the default scheme (FP32 and 16-bit storage):
+// one descriptor per state buffer, so its 18 planes must span less than 4 GiB.
 __host__ __device__ inline bool buffer_fits(const KParams &k, int storage) {
-  if (storage != kF16 && storage != kBF16) return false;
-  return 18ull * (unsigned long long)k.plane * 2ull < (1ull << 32);
+  unsigned long long esz = (storage == kF32) ? 4ull : ((storage == kF16 || storage == kBF16) ? 2ull : 0ull);
+  if (esz == 0) return false;
+  return 18ull * (unsigned long long)k.plane * esz < (1ull << 32);
+}
+
+// FP32 copies of the launch constants (KParams::f32), rounded as the kernels
+// would round them.
+inline void fill_f32_consts(KParams &k) {
+  KParams::F32 &f = k.f32;
+  f.R = (float)k.R;
+  f.T0 = (float)k.T0;
+  f.b = (float)k.b;
+  f.w1 = (float)k.w1;
+  f.w2 = (float)k.w2;
+  f.w3 = (float)k.w3;
+  f.w4 = (float)k.w4;
+  f.wh = (float)k.wh;
+  f.inv_tau_hf = (float)k.inv_tau_hf;
+  f.two_b = (float)(2.0 / k.b);
+  f.inv_RT0 = (float)(1.0 / (k.R * k.T0));
+  f.RT0f = (float)(k.R * k.T0);
+  f.dRT0 = (float)(k.R * k.T0 - (double)f.RT0f);
+  f.ax = (float)k.ax;
+  f.ay = (float)k.ay;
+  for (int s = 0; s < 4; ++s) {
+    f.wall_ux[s] = (float)k.wall_ux[s];
+    f.wall_uy[s] = (float)k.wall_uy[s];
+    f.wall_dth[s] = (float)k.wall_dth[s];
+  }
 }
 
 // Reduction record written per block by the moments kernel.
@@ -73,6 +107,7 @@ size_t store_bytes(int storage);
 hipError_t launch_step(const KParams &k, int storage, hipStream_t s);
 const char *step_kernel_name(const KParams &k, int storage);
 int step_waves_per_block();
+const char *batch_step_kernel_name(int storage);
 // one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
                              int storage, int parity, bool all_default, bool all_fit, hipStream_t s);

@@ -166,22 +166,42 @@ __device__ __forceinline__ Flags flags(const KParams &k) {
   return Flags{k.thermal, k.wall_rho, k.axf != nullptr, k.visc_mode == 1};
 }
 
+// Launch constants in the compute type: FP32 from the host-rounded copies,
+// FP64 from the doubles.
+
 template <class R, int M = 0>
 __device__ __forceinline__ Consts<R> make_consts(const KParams &k) {
   Consts<R> c;
-  c.R_ = (R)k.R;
-  c.T0 = (R)k.T0;
-  c.b = (R)k.b;
-  c.w1 = (R)k.w1;
-  c.w2 = (R)k.w2;
-  c.w3 = (R)k.w3;
-  c.w4 = (R)k.w4;
-  c.wh = (R)k.wh;
-  c.inv_tau_hf = (R)k.inv_tau_hf;
-  c.two_b = (R)(2.0 / k.b);
-  c.inv_RT0 = (R)(1.0 / (k.R * k.T0));
-  c.RT0f = (R)(k.R * k.T0);
-  c.dRT0 = (R)(k.R * k.T0 - (double)c.RT0f);
+  if constexpr (sizeof(R) == 4) {
+    const KParams::F32 &f = k.f32;
+    c.R_ = f.R;
+    c.T0 = f.T0;
+    c.b = f.b;
+    c.w1 = f.w1;
+    c.w2 = f.w2;
+    c.w3 = f.w3;
+    c.w4 = f.w4;
+    c.wh = f.wh;
+    c.inv_tau_hf = f.inv_tau_hf;
+    c.two_b = f.two_b;
+    c.inv_RT0 = f.inv_RT0;
+    c.RT0f = f.RT0f;
+    c.dRT0 = f.dRT0;
+  } else {
+    c.R_ = (R)k.R;
+    c.T0 = (R)k.T0;
+    c.b = (R)k.b;
+    c.w1 = (R)k.w1;
+    c.w2 = (R)k.w2;
+    c.w3 = (R)k.w3;
+    c.w4 = (R)k.w4;
+    c.wh = (R)k.wh;
+    c.inv_tau_hf = (R)k.inv_tau_hf;
+    c.two_b = (R)(2.0 / k.b);
+    c.inv_RT0 = (R)(1.0 / (k.R * k.T0));
+    c.RT0f = (R)(k.R * k.T0);
+    c.dRT0 = (R)(k.R * k.T0 - (double)c.RT0f);
+  }
   c.thermal = (M >= 1) ? 1 : k.thermal;
   c.correction = (M >= 1) ? 1 : k.correction;
   c.heq_mode = (M >= 1) ? 0 : k.heq_mode;
@@ -234,6 +254,9 @@ __device__ __forceinline__ void node_accel(const KParams &k, int y, int x, R &ax
     long long i = (long long)y * k.pitch + x;
     ax = reinterpret_cast<const R *>(k.axf)[i];
     ay = reinterpret_cast<const R *>(k.ayf)[i];
+  } else if constexpr (sizeof(R) == 4) {
+    ax = k.f32.ax;
+    ay = k.f32.ay;
   } else {
     ax = (R)k.ax;
     ay = (R)k.ay;
@@ -417,6 +440,38 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
   using LV = __attribute__((address_space(3))) void;
   const float *src = reinterpret_cast<const float *>(k.src);
   const RowSrc rs = row_src(k, y);
+  if constexpr (M == 2) {
+    // buffer addressing: one descriptor for the state buffer; plane and row
+    // (wave-uniform) in the scalar offset, the lane's column in the vector
+    // offset; bounce-back links carry their plane in the lane's offset
+    const __amdgpu_buffer_rsrc_t r = state_rsrc<kF32>(k.src, k);
+    if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
+      const unsigned cm = (unsigned)col.xm * 4u, cz = (unsigned)col.xc * 4u, cp = (unsigned)col.xp * 4u;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const unsigned rb = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) * 4u;
+        const unsigned vb = kEx[a] > 0 ? cm : (kEx[a] < 0 ? cp : cz);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + a * 64), 4, vb, plane_bytes<kF32>(k, a) + rb, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + (9 + a) * 64), 4, vb,
+                                                 plane_bytes<kF32>(k, a + 9) + rb, 0, 0);
+      }
+      return;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+      const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
+      const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
+      const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
+      const bool bb = ox || oy;
+      const int pa = bb ? kOpp[a] : a;
+      const unsigned vb = (bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx) * 4u + plane_bytes<kF32>(k, pa);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + a * 64), 4, vb, 0u, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + (9 + a) * 64), 4, vb + plane_bytes<kF32>(k, 9), 0u,
+                                               0, 0);
+    }
+    return;
+  }
   const long long hoff = 9 * k.plane;
   const bool th = flags<M>(k).thermal;
   if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
@@ -462,7 +517,14 @@ __device__ __forceinline__ void wall_node(const KParams &k, const Consts<R> &c, 
   const R thw = qw.th + dthw;
   const R aI_n = (side == kYlo) ? -ayI : ayI;
   const R aW_n = (side == kYlo) ? -ayW : ayW;
-  const R uwx = (R)k.wall_ux[side], uwy = (R)k.wall_uy[side];
+  R uwx, uwy;
+  if constexpr (sizeof(R) == 4) {
+    uwx = k.f32.wall_ux[side];
+    uwy = k.f32.wall_uy[side];
+  } else {
+    uwx = (R)k.wall_ux[side];
+    uwy = (R)k.wall_uy[side];
+  }
   const Flags fl = flags<M>(k);
   R drw;
   if (fl.wall_rho == 1) {
@@ -560,7 +622,11 @@ __device__ __forceinline__ void get_wall_row(const KParams &k, const Consts<type
   node_accel<R, M>(k, y, col.xc, axW, ayW);
   // wall temperature as a deviation from the wall row's reference; the O(1)
   // parts are formed in double on the host (wall_dth)
-  R dthw = flags<M>(k).thermal ? (R)k.wall_dth[side] : c.R_ * c.T0 - s.q.th;
+  R dthw = c.R_ * c.T0 - s.q.th;
+  if (flags<M>(k).thermal) {
+    if constexpr (sizeof(R) == 4) dthw = k.f32.wall_dth[side];
+    else dthw = (R)k.wall_dth[side];
+  }
   if (flags<M>(k).thermal && k.bc[side] == kWallAdiabatic) {
     // zero normal temperature gradient to second order, -3 T_w + 4 T_1 - T_2 = 0,
     // with the row two inside the wall evaluated here (ny >= 4: a fluid row)
@@ -620,12 +686,14 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
   const unsigned hn = (S == kF16 || S == kBF16) ? sr_node(own, step) : 0u;
   if constexpr (M == 2) {
+    // row and plane in the scalar offset, the column in the vector offset
     const __amdgpu_buffer_rsrc_t r = state_rsrc<S>(k.dst, k);
-    const unsigned vb = own * (unsigned)sizeof(ST);
+    const unsigned vb = (unsigned)col.xc * (unsigned)sizeof(ST);
+    const unsigned rb = (unsigned)y * (unsigned)k.pitch * (unsigned)sizeof(ST);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      Store<S>::stb(r, vb, plane_bytes<S>(k, a), P[a], sr_word(hn, a));
-      Store<S>::stb(r, vb, plane_bytes<S>(k, a + 9), Q[a], sr_word(hn, a + 9));
+      Store<S>::stb(r, vb, plane_bytes<S>(k, a) + rb, P[a], sr_word(hn, a));
+      Store<S>::stb(r, vb, plane_bytes<S>(k, a + 9) + rb, Q[a], sr_word(hn, a + 9));
     }
     return;
   }
@@ -645,9 +713,10 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 //   TCLBM_LDS_PULL            FP32 rows pulled one row ahead into LDS (1)
 //   TCLBM_SCHEME_SPECIAL      compile-time instantiation of the default scheme (1)
 //   TCLBM_BUFFER_ADDR         buffer-resource addressing for it, 16-bit storage (1)
-//   TCLBM_F32_WAVES_PER_EU    occupancy cap of the FP32 step kernel (0: none)
+//   TCLBM_F32_WAVES_PER_EU    occupancy cap of the FP32 step kernels (3)
 //   TCLBM_WAVES_PER_EU        occupancy cap of the 16-bit step kernels (3)
-//   TCLBM_BATCH_WAVES_PER_EU  occupancy cap of the FP32/16-bit batch kernels (3)
+//   TCLBM_BATCH_WAVES_PER_EU  occupancy cap of the 16-bit batch kernels (3)
+//   TCLBM_BATCH32_WAVES_PER_EU  occupancy cap of the FP32 batch kernels (3)
 //   TCLBM_ROW_GROUP           rows per block for FP32 lattices of single-row
 //                             strips, neighbours' u_y(1 - theta) shared in LDS
 //                             (4; 1: one independent wave per row)
@@ -666,7 +735,7 @@ constexpr int kStepWaves = TCLBM_STEP_WAVES;
 #define TCLBM_BUFFER_ADDR 1
 #endif
 #ifndef TCLBM_F32_WAVES_PER_EU
-#define TCLBM_F32_WAVES_PER_EU 0
+#define TCLBM_F32_WAVES_PER_EU 3
 #endif
 #if TCLBM_F32_WAVES_PER_EU > 0
 #define TCLBM_F32_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_F32_WAVES_PER_EU, TCLBM_F32_WAVES_PER_EU)))
@@ -692,6 +761,20 @@ constexpr int kRowGroup = TCLBM_ROW_GROUP;
 #define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
 #else
 #define TCLBM_BATCH_OCC
+#endif
+// occupancy cap of the FP32 batch kernels (0: none).  Their default-scheme
+// instantiations fit in 128 registers, but 4 waves per SIMD measured slower
+// than 3 (256-lattice batch 1150 vs 1086 us, 8192x4096 alone 1266 vs
+// 1179 us): the kernels are bound by their memory access pattern, and more
+// waves in flight only spread it over more rows.
+#ifndef TCLBM_BATCH32_WAVES_PER_EU
+#define TCLBM_BATCH32_WAVES_PER_EU 3
+#endif
+#if TCLBM_BATCH32_WAVES_PER_EU > 0
+#define TCLBM_BATCH32_OCC \
+  __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH32_WAVES_PER_EU, TCLBM_BATCH32_WAVES_PER_EU)))
+#else
+#define TCLBM_BATCH32_OCC
 #endif
 
 // The march of one wave over its (x tile, strip) of lattice k.
@@ -979,6 +1062,11 @@ __global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH_OCC void batch_step_ke
   batch_body<S, MB>(tab, wave_start, n_inst, parity);
 }
 template <int MB>
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH32_OCC void batch_step_kernel_f32(
+    const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity) {
+  batch_body<kF32, MB>(tab, wave_start, n_inst, parity);
+}
+template <int MB>
 __global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel_f64(const KParams *__restrict__ tab,
                                                                          const int *__restrict__ wave_start,
                                                                          int n_inst, int parity) {
@@ -1000,7 +1088,7 @@ hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int 
   } while (0)
   switch (storage) {
     case kF32:
-      TCLBM_BATCH_LAUNCH((batch_step_kernel<kF32, 0>), (batch_step_kernel<kF32, 1>), (batch_step_kernel<kF32, 1>));
+      TCLBM_BATCH_LAUNCH((batch_step_kernel_f32<0>), (batch_step_kernel_f32<1>), (batch_step_kernel_f32<2>));
       break;
     case kF16:
       TCLBM_BATCH_LAUNCH((batch_step_kernel<kF16, 0>), (batch_step_kernel<kF16, 1>), (batch_step_kernel<kF16, 2>));
@@ -1020,6 +1108,16 @@ hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int 
 
 int step_waves_per_block() { return kStepWaves; }
 
+const char *batch_step_kernel_name(int storage) {
+  switch (storage) {
+    case kF32: return "batch_step_kernel_f32";
+    case kF16:
+    case kBF16: return "batch_step_kernel";
+    case kF64: return "batch_step_kernel_f64";
+    default: return "";
+  }
+}
+
 hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
   const int waves = k.n_xtiles * k.n_strips;
   const int blocks = (waves + kStepWaves - 1) / kStepWaves;
@@ -1030,14 +1128,18 @@ hipError_t launch_step(const KParams &k, int storage, hipStream_t s) {
     case kF32:
       if (d && k.strip_rows == 1 && kRowGroup > 1) {
         const int groups = (k.ny + kRowGroup - 1) / kRowGroup;
-        if (k.bc[kYlo] == kPeriodic)
-          hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, false>), dim3(groups * k.n_xtiles),
-                             dim3(64 * kRowGroup), 0, s, k);
-        else
-          hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, true>), dim3(groups * k.n_xtiles),
-                             dim3(64 * kRowGroup), 0, s, k);
-      } else if (d && k.strip_rows == 1 && kStepWaves != 1)
-        hipLaunchKernelGGL((step_kernel<kF32, 1, 1>), dim3(waves), dim3(64), 0, s, k);
+        const dim3 gg(groups * k.n_xtiles), gb(64 * kRowGroup);
+        if (k.bc[kYlo] == kPeriodic) {
+          if (b) hipLaunchKernelGGL((row_group_kernel<kF32, 2, kRowGroup, false>), gg, gb, 0, s, k);
+          else hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, false>), gg, gb, 0, s, k);
+        } else {
+          if (b) hipLaunchKernelGGL((row_group_kernel<kF32, 2, kRowGroup, true>), gg, gb, 0, s, k);
+          else hipLaunchKernelGGL((row_group_kernel<kF32, 1, kRowGroup, true>), gg, gb, 0, s, k);
+        }
+      } else if (d && k.strip_rows == 1 && kStepWaves != 1) {
+        if (b) hipLaunchKernelGGL((step_kernel<kF32, 2, 1>), dim3(waves), dim3(64), 0, s, k);
+        else hipLaunchKernelGGL((step_kernel<kF32, 1, 1>), dim3(waves), dim3(64), 0, s, k);
+      } else if (b) hipLaunchKernelGGL((step_kernel<kF32, 2, kStepWaves>), grid, block, 0, s, k);
       else if (d) hipLaunchKernelGGL((step_kernel<kF32, 1, kStepWaves>), grid, block, 0, s, k);
       else hipLaunchKernelGGL((step_kernel<kF32, 0, kStepWaves>), grid, block, 0, s, k);
       break;

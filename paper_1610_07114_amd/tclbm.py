@@ -56,7 +56,7 @@ EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_s
            "tclbm_step_kernel", "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
            "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
            "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_set_strip_rows",
-           "tclbm_batch_strip_rows", "tclbm_batch_destroy"]
+           "tclbm_batch_strip_rows", "tclbm_batch_step_kernel", "tclbm_batch_destroy"]
 
 
 def _load():
@@ -119,6 +119,8 @@ def _load():
     lib.tclbm_batch_set_strip_rows.restype = ctypes.c_int
     lib.tclbm_batch_strip_rows.argtypes = [H]
     lib.tclbm_batch_strip_rows.restype = ctypes.c_int32
+    lib.tclbm_batch_step_kernel.argtypes = [H]
+    lib.tclbm_batch_step_kernel.restype = ctypes.c_char_p
     lib.tclbm_batch_destroy.argtypes = [H]
     lib.tclbm_batch_destroy.restype = ctypes.c_int
     return lib
@@ -264,6 +266,10 @@ def tclbm_batch_strip_rows(b) -> int:
     return int(_lib.tclbm_batch_strip_rows(b))
 
 
+def tclbm_batch_step_kernel(b) -> str:
+    return _lib.tclbm_batch_step_kernel(b).decode()
+
+
 def tclbm_batch_destroy(b):
     _chk(_lib.tclbm_batch_destroy(b))
 
@@ -371,6 +377,11 @@ class Batch:
     @property
     def strip_rows(self) -> int:
         return tclbm_batch_strip_rows(self.h)
+
+    @property
+    def kernel(self) -> str:
+        """Name of the kernel one batch step launches (as in a kernel trace)."""
+        return tclbm_batch_step_kernel(self.h)
 
     def close(self):
         if self.h is not None:

@@ -457,6 +457,14 @@ def test_step_kernel_names(T):
     lat.set_tuning(1, 16)
     assert lat.kernel == "step_kernel"
     lat.close()
+    for storage, name in (("f32", "batch_step_kernel_f32"), ("f16", "batch_step_kernel"),
+                          ("f64", "batch_step_kernel_f64")):
+        lat = T.Lattice(case, storage=storage, stream=stream)
+        b = T.Batch([lat])
+        assert b.kernel == name, (storage, b.kernel)
+        b.step(2)
+        b.close()
+        lat.close()
 
 
 @pytest.mark.parametrize("label,make", [
