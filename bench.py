@@ -358,12 +358,14 @@ def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=
         # (everything queued at t = 0) of a calibration stream from the same
         # distribution, divided by the mean work of the stream's own requests
         # (the work per request is heavy-tailed, ~N^3)
-        calib = S.make_requests(max(40, n_requests // 8), rate=1.0, seed=seed + 1000, time_units=time_units)
+        # (fewer calibration requests when each one is long)
+        n_cal = max(40, n_requests // 8) if time_units <= 1.0 else max(8, n_requests // 4)
+        calib = S.make_requests(n_cal, rate=1.0, seed=seed + 1000, time_units=time_units)
         for r in calib:
             r.arrival = 0.0
         srv = S.Server(storage=storage)
         t0 = time.perf_counter()
-        res = srv.run(calib, realtime=False)
+        res = srv.run(calib, realtime=False, log=log if time_units > 1.0 else None)
         cap_wall = time.perf_counter() - t0
         cal_lups = sum(r.nx * r.ny * r.steps for r in res) / cap_wall
         capacity = cal_lups / work
@@ -376,7 +378,8 @@ def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=
             f"{cap_wall:.1f} s), mean work {work:.3g} LUP -> capacity {capacity:.2f} solves/s; stream of "
             f"{len(reqs)} requests at {rate:.2f}/s over {span:.1f} s")
         t0 = time.perf_counter()
-        res = srv.run(reqs, realtime=True)
+        # long requests: one line per completed request (progress of the run)
+        res = srv.run(reqs, realtime=True, log=log if time_units > 1.0 else None)
         wall = time.perf_counter() - t0
         summ = S.summarize([r for r in res if r.rid not in ref], wall)
         out[storage] = {"arrival_rate_per_s": round(rate, 3), "load_vs_capacity": load,
@@ -392,7 +395,7 @@ def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=
         # the last stream's arrivals
         srv1 = S.Server(storage="f32", max_slots=1)
         t0 = time.perf_counter()
-        res1 = srv1.run(reqs, realtime=True)
+        res1 = srv1.run(reqs, realtime=True, log=log if time_units > 1.0 else None)
         wall1 = time.perf_counter() - t0
         nu_fp32 = {r.rid: r.nu for r in res1 if r.rid in ref}
         out["single_lattice_fp32"] = {**S.summarize([r for r in res1 if r.rid not in ref], wall1),
