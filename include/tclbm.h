@@ -122,6 +122,19 @@ typedef struct {
                              from that w1 at constant Pr (tau_f is then unused) */
   double mu0;             /* reference dynamic viscosity (> 0 when
                              viscosity_mode = 1) */
+  int32_t energy_df;      /* 0: total-energy DF (Section 4; default); 1: the
+                             internal-energy DF that Section 5D uses for
+                             Rayleigh-Benard convection so that no viscous
+                             heating enters (the paper cites it without stating
+                             it).  Reading: the second DF carries rho e,
+                             e = b R T/2, relaxes by BGK at w_h towards
+                             e f^eq, and receives a body-force source of first
+                             moment e rho a with the (1 - w_h/2) factor; then
+                             T = 2 sum(g)/(rho b R), the diffusivity is
+                             R T (1/w_h - 1/2) = nu/Pr, and neither viscous
+                             dissipation nor pressure work enters.
+                             heq_moments, h_collision and h_force are ignored;
+                             the energy sum of tclbm_sums is then sum rho e */
 } tclbm_params;
 
 /* FP64 whole-lattice reductions of the state the next step would see

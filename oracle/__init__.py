@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("ax_field", ctypes.POINTER(ctypes.c_double)), ("ay_field", ctypes.POINTER(ctypes.c_double)),
         ("h_force", ctypes.c_int32),
         ("viscosity_mode", ctypes.c_int32), ("mu0", ctypes.c_double),
+        ("energy_df", ctypes.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ def lib():
         _lib.orc_feq.argtypes = [ctypes.c_double] * 4 + [d]
         _lib.orc_heq.argtypes = [ctypes.c_double] * 5 + [d]
         _lib.orc_heq_mode.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int, d]
+        _lib.orc_geq.argtypes = [ctypes.c_double] * 5 + [d]
         _lib.orc_node_macros.argtypes = [P, d, d, ctypes.c_double, ctypes.c_double, d, d, d, d]
         _lib.orc_collide_node.argtypes = [P, d, d] + [ctypes.c_double] * 8 + [d, d]
         _lib.orc_init.argtypes = [P, d, d, d, d, d, d]
@@ -171,6 +173,13 @@ def heq(rho, ux, uy, RT, b, mode: int = 1) -> np.ndarray:
     return out
 
 
+def geq(rho, ux, uy, RT, b) -> np.ndarray:
+    """Internal-energy DF equilibrium (Section 5D reading): e f^eq, e = b RT/2."""
+    out = np.zeros(9)
+    lib().orc_geq(rho, ux, uy, RT, b, _p(out))
+    return out
+
+
 # ---- lattice -------------------------------------------------------------------
 
 @dataclass
@@ -199,6 +208,7 @@ class Params:
     h_force: int = 1
     viscosity_mode: int = 0   # 1: mu = mu0 T/T0 (Section 5B), per-node w1 from Eq. (29)
     mu0: float = 0.0
+    energy_df: int = 0        # 1: the internal-energy DF of Section 5D (orc_geq)
     ax_field: Optional[np.ndarray] = None
     ay_field: Optional[np.ndarray] = None
     _keep: list = field(default_factory=list, repr=False)
@@ -207,7 +217,7 @@ class Params:
         c = _Params()
         for name in ("nx", "ny", "R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay",
                      "thermal", "correction", "wall_rho", "heq_moments", "h_collision", "h_force",
-                     "viscosity_mode", "mu0"):
+                     "viscosity_mode", "mu0", "energy_df"):
             setattr(c, name, getattr(self, name))
         for i in range(4):
             c.bc[i] = int(self.bc[i])

@@ -61,7 +61,10 @@
  *              H = 39);
  *   mu(T)      mu = mu0 T/T0 of Section 5B enters through Eq. (29) at each node,
  *              1/w1 = mu/p + 1/2 = mu0/(rho R T0) + 1/2, and w_h, tau_hf follow
- *              from that w1 at constant Pr as everywhere else.
+ *              from that w1 at constant Pr as everywhere else;
+ *   e-DF       Section 5D's internal-energy DF, which the paper cites without
+ *              stating: g^eq = e f^eq, BGK at w_h, a force source with first
+ *              moment e rho a (orc_geq).
  *
  * Build:  gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -113,6 +116,8 @@ typedef struct {
                         * 0 none (Section 4 as printed) */
   int32_t viscosity_mode; /* 0: w1 = 1/tau_f; 1: mu = mu0 T/T0 (Section 5B) */
   double mu0;
+  int32_t energy_df;   /* 0: total-energy DF (Section 4); 1: internal-energy DF
+                        * (Section 5D's Rayleigh-Benard runs), see orc_geq */
 } orc_params;
 
 static double pw(double v, int n) {
@@ -320,6 +325,27 @@ void orc_heq(double rho, double ux, double uy, double RT, double b, double heq[9
   orc_heq_mode(rho, ux, uy, RT, b, 1, heq);
 }
 
+/* Section 5D runs Rayleigh-Benard convection with an internal-energy DF in
+ * place of the total-energy one, so that no viscous heating enters; the paper
+ * cites the model without stating it.  Reading: the DF g carries rho e, with
+ * e = b R T/2 the internal energy per unit mass, and its equilibrium is the
+ * density equilibrium scaled by e, g^eq_a = e f^eq_a (moments rho e, rho e u,
+ * e (p I + rho u u)).  A Chapman-Enskog expansion of the BGK update
+ * g* = g - w_h (g - g^eq) + (1 - w_h/2) G then gives
+ *   d(rho e)/dt + div(rho e u) = div(p (1/w_h - 1/2) grad e),
+ * i.e. rho c_v DT/Dt = div(kappa grad T) with thermal diffusivity
+ * R T (1/w_h - 1/2) = nu/Pr at the same w_h as the total-energy DF: no
+ * viscous dissipation and no pressure work.  Without a source the expansion
+ * leaves a spurious flux -(1/w_h - 1/2) e rho a under a body force (the force
+ * changes the equilibrium flux rho e u within a step); G, with first moment
+ * e rho a on the axis links and no other moment, supplies that change. */
+void orc_geq(double rho, double ux, double uy, double RT, double b, double geq[9]) {
+  double feq[9];
+  orc_feq(rho, ux, uy, RT, feq);
+  double e = 0.5 * b * RT;
+  for (int a = 0; a < 9; ++a) geq[a] = e * feq[a];
+}
+
 /* Derived relaxation constants. */
 typedef struct {
   double b, RT0, w1, wh, inv_tau_hf;
@@ -356,7 +382,8 @@ static double node_ay(const orc_params *p, long i) { return p->ay_field ? p->ay_
 
 /* Eq. (20) and the temperature of Section 4:
  * rho = sum fbar, rho u = sum fbar e + F/2 (F = rho a),
- * T = 2/(b R) (sum hbar / rho - u^2/2). */
+ * T = 2/(b R) (sum hbar / rho - u^2/2);
+ * with the internal-energy DF (orc_geq) T = 2/(b R) sum g / rho. */
 void orc_node_macros(const orc_params *p, const double fb[9], const double hb[9], double ax, double ay,
                      double *rho, double *ux, double *uy, double *T) {
   orc_derived d = derive(p);
@@ -372,7 +399,10 @@ void orc_node_macros(const orc_params *p, const double fb[9], const double hb[9]
   if (p->thermal) {
     double hs = 0.0;
     for (int a = 0; a < 9; ++a) hs += hb[a];
-    t = 2.0 / (d.b * p->R) * (hs / r - 0.5 * (vx * vx + vy * vy));
+    if (p->energy_df == 1)
+      t = 2.0 / (d.b * p->R) * (hs / r);
+    else
+      t = 2.0 / (d.b * p->R) * (hs / r - 0.5 * (vx * vx + vy * vy));
   }
   *rho = r;
   *ux = vx;
@@ -437,6 +467,19 @@ void orc_collide_node(const orc_params *p, const double fb[9], const double hb[9
 
   if (!p->thermal) {
     for (int a = 0; a < 9; ++a) hout[a] = 0.0;
+    return;
+  }
+
+  if (p->energy_df == 1) {
+    /* internal-energy DF (orc_geq): BGK towards e f^eq with the force source G */
+    double geq[9], G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    orc_geq(rho, ux, uy, RT, d.b, geq);
+    double ge = 0.5 * rho * (0.5 * d.b * RT); /* half of rho e */
+    G[1] = ge * ax;
+    G[3] = -ge * ax;
+    G[2] = ge * ay;
+    G[4] = -ge * ay;
+    for (int a = 0; a < 9; ++a) hout[a] = hb[a] - d.wh * (hb[a] - geq[a]) + (1.0 - 0.5 * d.wh) * G[a];
     return;
   }
 
@@ -572,7 +615,11 @@ static void wall_prestep(const orc_params *p, double *f, double *h) {
       orc_source_moments(node_ax(p, i_f), node_ay(p, i_f), vx, vy, smf);
       orc_pops_from_moments(r, smf, Sf);
       for (int a = 0; a < 9; ++a) f[a * n + ib] = (fw[a] - 0.5 * Sw[a]) + (fb[a] - (ff[a] - 0.5 * Sf[a]));
-      if (p->thermal) {
+      if (p->thermal && p->energy_df == 1) {
+        orc_geq(rw, p->wall_ux[side], p->wall_uy[side], p->R * Tw, d.b, hw);
+        orc_geq(r, vx, vy, p->R * t, d.b, hf);
+        for (int a = 0; a < 9; ++a) h[a * n + ib] = hw[a] + (hb[a] - hf[a]);
+      } else if (p->thermal) {
         orc_heq_mode(rw, p->wall_ux[side], p->wall_uy[side], p->R * Tw, d.b, p->heq_moments, hw);
         orc_heq_mode(r, vx, vy, p->R * t, d.b, p->heq_moments, hf);
         for (int a = 0; a < 9; ++a) h[a * n + ib] = hw[a] + (hb[a] - hf[a]);
@@ -601,13 +648,14 @@ int orc_check_params(const orc_params *p) {
     if (p->bc[s] < 0 || p->bc[s] > 3) return 1;
   if (p->viscosity_mode < 0 || p->viscosity_mode > 1 || (p->viscosity_mode == 1 && !(p->mu0 > 0.0))) return 1;
   if (p->wall_rho < 0 || p->wall_rho > 2 || p->heq_moments < 0 || p->heq_moments > 1 || p->h_collision < 0 || p->h_collision > 1 || p->h_force < 0 || p->h_force > 1) return 1;
+  if (p->energy_df < 0 || p->energy_df > 1) return 1;
   if ((p->bc[ORC_XLO] == ORC_PERIODIC) != (p->bc[ORC_XHI] == ORC_PERIODIC)) return 1;
   if ((p->bc[ORC_YLO] == ORC_PERIODIC) != (p->bc[ORC_YHI] == ORC_PERIODIC)) return 1;
   if (is_wall(p->bc[ORC_XLO]) || is_wall(p->bc[ORC_XHI])) return 1; /* walls on y sides only */
   return 0;
 }
 
-/* Initial state (fbar = f^eq - S/2, hbar = h^eq) from macroscopic fields. */
+/* Initial state (fbar = f^eq - S/2, hbar = h^eq or g^eq) from macroscopic fields. */
 int orc_init(const orc_params *p, const double *rho, const double *ux, const double *uy, const double *T,
              double *f, double *h) {
   if (orc_check_params(p)) return 1;
@@ -621,7 +669,10 @@ int orc_init(const orc_params *p, const double *rho, const double *ux, const dou
     orc_feq(rho[i], ux[i], uy[i], RT, feq);
     orc_source_moments(node_ax(p, i), node_ay(p, i), ux[i], uy[i], sm);
     orc_pops_from_moments(rho[i], sm, S);
-    orc_heq_mode(rho[i], ux[i], uy[i], RT, d.b, p->heq_moments, heq);
+    if (p->energy_df == 1)
+      orc_geq(rho[i], ux[i], uy[i], RT, d.b, heq);
+    else
+      orc_heq_mode(rho[i], ux[i], uy[i], RT, d.b, p->heq_moments, heq);
     for (int a = 0; a < 9; ++a) {
       f[a * n + i] = feq[a] - 0.5 * S[a];
       h[a * n + i] = p->thermal ? heq[a] : 0.0;

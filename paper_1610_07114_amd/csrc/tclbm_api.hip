@@ -76,6 +76,7 @@ bool valid_params(const tclbm_params *p) {
   if (p->heq_moments < 0 || p->heq_moments > 1) return false;
   if (p->h_collision < 0 || p->h_collision > 1) return false;
   if (p->h_force < 0 || p->h_force > 1) return false;
+  if (p->energy_df != 0 && p->energy_df != 1) return false;
   if (p->accel_field != 0 && p->accel_field != 1) return false;
   if (p->viscosity_mode != 0 && p->viscosity_mode != 1) return false;
   if (p->viscosity_mode == 1 && !(p->mu0 > 0.0 && std::isfinite(p->mu0))) return false;
@@ -129,6 +130,13 @@ void fill_kparams(tclbm_ctx *c) {
   k.heq_mode = p.heq_moments;
   k.h_coll = p.h_collision;
   k.h_force = p.h_force;
+  if (p.energy_df == 1) {
+    // internal-energy DF: equilibrium mode 2 (e f^eq), BGK with its own force
+    // source (the total-energy switches do not apply)
+    k.heq_mode = 2;
+    k.h_coll = 1;
+    k.h_force = 0;
+  }
   k.wall_rho = p.wall_rho;
   k.visc_mode = p.viscosity_mode;
   k.mu0_RT0 = p.mu0 / (p.R * p.T0);
@@ -233,8 +241,9 @@ void build_refs(const tclbm_params &p, const double *rho, const double *T, std::
     }
     rr[2 * y] = (R)(rs / nx);
     rr[2 * y + 1] = (R)(p.R * (p.thermal ? ts / nx : p.T0));
-    RowRef<double> q = make_ref<double>((double)rr[2 * y], (double)rr[2 * y + 1], b, p.heq_moments);
-    ref_pops<double>(q, p.thermal, p.heq_moments, &rpop[9 * (size_t)y], &spop[9 * (size_t)y]);
+    const int hm = p.energy_df ? 2 : p.heq_moments;
+    RowRef<double> q = make_ref<double>((double)rr[2 * y], (double)rr[2 * y + 1], b, hm);
+    ref_pops<double>(q, p.thermal, hm, &rpop[9 * (size_t)y], &spop[9 * (size_t)y]);
   }
   static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   for (int y = 0; y < ny; ++y)

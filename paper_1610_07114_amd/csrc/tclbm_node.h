@@ -82,12 +82,21 @@ struct RowRef {
   R rho, th, E, S2, S22;
 };
 
+// Rest reference of a row.  heq_mode 0/1: total-energy DF (raw moments E,
+// S2 = th (E + th), S22 = th^2 (E + 2 th) or 0); heq_mode 2: internal-energy
+// DF, whose rest populations are e times the density ones (S2 = th E,
+// S22 = th^2 E).
 template <class R>
 TC_HD RowRef<R> make_ref(R rho, R th, R b, int heq_mode) {
   RowRef<R> q;
   q.rho = rho;
   q.th = th;
   q.E = R(0.5) * b * th;
+  if (heq_mode == 2) {
+    q.S2 = th * q.E;
+    q.S22 = th * th * q.E;
+    return q;
+  }
   q.S2 = th * (q.E + th);
   q.S22 = (heq_mode == 1) ? R(0) : th * th * (q.E + R(2) * th);
   return q;
@@ -173,8 +182,12 @@ TC_HD Macro<R> macros(const Consts<R> &c, const RowRef<R> &q, const R *d, const 
   m.uy = jy * ir + R(0.5) * ay;
   if (c.thermal) {
     m.sg = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
-    // theta - theta_r = (2/b) ((sum g - drho E_r)/rho - u^2/2)
-    m.dth = c.two_b * ((m.sg - m.drho * q.E) * ir - R(0.5) * (m.ux * m.ux + m.uy * m.uy));
+    // theta - theta_r = (2/b) ((sum g - drho E_r)/rho - u^2/2); the
+    // internal-energy DF (heq_mode 2) carries no kinetic part
+    if (c.heq_mode == 2)
+      m.dth = c.two_b * ((m.sg - m.drho * q.E) * ir);
+    else
+      m.dth = c.two_b * ((m.sg - m.drho * q.E) * ir - R(0.5) * (m.ux * m.ux + m.uy * m.uy));
   } else {
     m.sg = R(0);
     m.dth = c.R_ * c.T0 - q.th;
@@ -215,6 +228,23 @@ TC_HD void heq_dev(const Consts<R> &c, const RowRef<R> &q, R drho, R ux, R uy, R
   const R rho = q.rho + drho, th = q.th + dth;
   const R rr = q.rho, rE = rr * q.E, rS2 = rr * q.S2;
   const R ux2 = ux * ux, uy2 = uy * uy;
+  if (c.heq_mode == 2) {
+    // internal-energy DF: g^eq = e f^eq, e = b th/2; against the reference
+    // e_r r: e (f^eq - r) + (e - e_r) r
+    R fd[9];
+    feq_dev(q, drho, ux, uy, dth, fd);
+    const R de = R(0.5) * c.b * dth, e = q.E + de;
+    const R p0 = R(1) - q.th, p1 = R(0.5) * q.th;
+    const R r0 = rr * p0 * p0, r1 = rr * p0 * p1, r5 = rr * p1 * p1;
+    out[0] = e * fd[0] + de * r0;
+#pragma unroll
+    for (int a = 1; a <= 4; ++a) out[a] = e * fd[a] + de * r1;
+#pragma unroll
+    for (int a = 5; a <= 8; ++a) out[a] = e * fd[a] + de * r5;
+    (void)sg;
+    (void)rho;
+    return;
+  }
   if (c.heq_mode == 1) {
     R E = R(0.5) * (c.b * th + ux2 + uy2);
     R A = E + th, B = E + R(2) * th, C = th * A, u2 = ux2 + uy2;
@@ -313,6 +343,23 @@ TC_HD void collide(const Consts<R> &c, const RowRef<R> &q, const R *d, const R *
   }
 
   if (!c.thermal) return;
+
+  if (c.heq_mode == 2) {
+    // Internal-energy DF: BGK towards e f^eq, plus the force source whose
+    // only moment is e rho a (half on each axis link), with the (1 - w_h/2)
+    // factor; no coupling source.
+    R he[9];
+    heq_dev(c, q, m.drho, ux, uy, m.dth, m.sg, he);
+    const R ge = R(0.5) * (R(1) - R(0.5) * c.wh) * rho * (R(0.5) * c.b * th);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Q[a] = g[a] - c.wh * (g[a] - he[a]);
+    Q[1] += ge * ax;
+    Q[3] -= ge * ax;
+    Q[2] += ge * ay;
+    Q[4] -= ge * ay;
+    if (kBalance) Q[0] = energy_balance(m.sg, Q);
+    return;
+  }
 
   // f - f^eq with f = fbar + S/2 + C/2: central moments, then populations.
   R dd[3][3];

@@ -37,6 +37,7 @@ class tclbm_params(ctypes.Structure):
         ("bc", ctypes.c_int32 * 4),
         ("wall_ux", ctypes.c_double * 4), ("wall_uy", ctypes.c_double * 4), ("wall_T", ctypes.c_double * 4),
         ("viscosity_mode", ctypes.c_int32), ("mu0", ctypes.c_double),
+        ("energy_df", ctypes.c_int32),
     ]
 
 
@@ -284,7 +285,7 @@ class Lattice:
         self.case = case
         p = tclbm_default_params(case.nx, case.ny)
         for name in ("R", "T0", "gamma", "Pr", "tau_f", "w2", "w3", "w4", "ax", "ay", "thermal", "correction",
-                     "viscosity_mode", "mu0"):
+                     "viscosity_mode", "mu0", "energy_df"):
             setattr(p, name, getattr(case, name))
         p.storage = STORE[storage]
         p.accel_field = 1 if case.ax_field is not None else 0

@@ -60,6 +60,7 @@ class Case:
     ay_field: Optional[np.ndarray] = None
     viscosity_mode: int = 0              # 1: mu = mu0 T/T0 (Section 5B)
     mu0: float = 0.0
+    energy_df: int = 0                   # 1: internal-energy DF (Section 5D)
     steps: int = 0                       # nominal run length of the problem
     meta: dict = field(default_factory=dict)
 
@@ -174,6 +175,19 @@ def rayleigh_benard(nx: int = 512, ny: int = 256, Ra: float = 1e5, Pr: float = 0
         ay=-P["g"], bc=(PERIODIC, PERIODIC, WALL, WALL), wall_T=(1.0, 1.0, Tb, Tt),
         rho=rho, ux=_full(ny, nx, 0.0), uy=_full(ny, nx, 0.0), T=T, steps=steps,
         meta=dict(Ra=Ra, H=H, dT=dT, kappa=P["kappa"], nu=P["nu"], g=P["g"], uc=uc, seed=seed))
+
+
+TABLE3_RA = (2500.0, 5000.0, 10000.0, 30000.0, 50000.0)
+
+
+def rb_table3(Ra: float, seed: int = 1) -> Case:
+    """Section 5D's Nu(Ra) runs: 6% temperature difference about T0 = 1,
+    u_c = 0.08, Pr = 0.71, w2 = w3 = w4 = 1, a 2:1 box with N_y = 80 below
+    Ra = 1e4, 100 below 5e4 and 150 above, the internal-energy DF, from the
+    conduction state with a seeded 1e-3 temperature perturbation."""
+    ny = 80 if Ra < 1e4 else (100 if Ra < 5e4 else 150)
+    return rayleigh_benard(nx=2 * ny, ny=ny, Ra=Ra, Pr=0.71, dT=0.06, uc=0.08, noise=1e-3,
+                           seed=seed).with_(energy_df=1)
 
 
 # --------------------------------------------------------------------------------

@@ -6,6 +6,7 @@ compare against.  Calls only the oracle and the seeded input generators.
   python tests/golden/make_nu_golden.py rb512   # 512x256 Rayleigh-Benard, 2e5 steps
   python tests/golden/make_nu_golden.py fields  # final FP64 fields of the steady subset
   python tests/golden/make_nu_golden.py onset   # kinetic-energy growth rates near Ra_c
+  python tests/golden/make_nu_golden.py table3  # Section 5D Nu(Ra) with the internal-energy DF
 
 Nu follows the Section 5D definition (oracle.nusselt).  A run lasts 120 H/u_c
 (the batched subset) or 2e5 steps (512x256); Nu is sampled on a fixed step
@@ -171,6 +172,24 @@ def main():
                    histories=[dict(steps=t, kinetic=e) for t, e in hist])
         print("sigma", sig, "Ra_c", out["Ra_c"], flush=True)
         path = os.path.join(HERE, "rb_onset_fp64.json")
+    elif which == "table3":
+        # Table 3's five Rayleigh numbers at the paper's resolutions; 150 flow
+        # times at Ra 2500 (slow growth near onset), 100 elsewhere
+        cases = [W.rb_table3(Ra) for Ra in W.TABLE3_RA]
+        jobs = []
+        for c in cases:
+            every, total, avg_from = schedule(c.meta["H"], c.meta["uc"], 150.0 if c.meta["Ra"] < 3000 else 100.0)
+            jobs.append((c, every, total, avg_from, int(os.environ.get("NU_THREADS", "2"))))
+        with ProcessPoolExecutor(max_workers=int(os.environ.get("NU_WORKERS", "4"))) as ex:
+            hist = list(ex.map(run_history, jobs))
+        out = dict(workload="rb_table3: 2N x N, N 80/100/150, dT 0.06, u_c 0.08, Pr 0.71, internal-energy DF, "
+                            "seed 1, noise 1e-3", runs=[])
+        for c, (_, every, total, avg_from, _), h in zip(cases, jobs, hist):
+            out["runs"].append(dict(Ra=c.meta["Ra"], nx=c.nx, ny=c.ny, every=every, total=total,
+                                    avg_from=avg_from, **h))
+            print(f"Ra {c.meta['Ra']:g} {c.nx}x{c.ny}: Nu {h['nu_mean']:.6f} unsteadiness {h['unsteadiness']:.2e} "
+                  f"({h['seconds']} s)", flush=True)
+        path = os.path.join(HERE, "rb_table3_internal_fp64.json")
     elif which == "fields":
         # final state of every batched instance whose Nu ended steady (window
         # variation < 2e-3): the start of the 16-bit steady-state checks

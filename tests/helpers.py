@@ -31,7 +31,7 @@ def oracle_params(case, **over) -> O.Params:
               w2=case.w2, w3=case.w3, w4=case.w4, ax=case.ax, ay=case.ay, thermal=case.thermal,
               correction=case.correction, bc=case.bc, wall_ux=case.wall_ux, wall_uy=case.wall_uy,
               wall_T=case.wall_T, ax_field=case.ax_field, ay_field=case.ay_field,
-              viscosity_mode=case.viscosity_mode, mu0=case.mu0)
+              viscosity_mode=case.viscosity_mode, mu0=case.mu0, energy_df=case.energy_df)
     kw.update(over)
     return O.Params(**kw)
 

@@ -152,10 +152,13 @@ def _node_case(seed):
     Pr = rng.uniform(0.5, 7)
     hm, hc, hfo = int(rng.integers(0, 2)), int(rng.integers(0, 2)), int(rng.integers(0, 2))
     th = 0 if seed % 7 == 3 else 1
+    edf = 1 if seed % 5 == 1 else 0     # internal-energy DF (Section 5D)
     p = O.Params(nx=3, ny=3, tau_f=tau, w2=w2, w3=w3, w4=w4, gamma=g, Pr=Pr, heq_moments=hm, h_collision=hc,
-                 h_force=hfo, thermal=th)
+                 h_force=hfo, thermal=th, energy_df=edf)
     b, R, w1 = 2 / (g - 1), 1 / 3, 1 / tau
     wh = 1 / ((tau - 0.5) / Pr + 0.5)
+    if edf:  # the library's internal encoding: equilibrium mode 2, BGK, no total-energy force term
+        hm, hc, hfo = 2, 1, 0
     cst = np.array([R, 1.0, b, w1, w2, w3, w4, wh, w1 * (Pr - 1), th, 1, hm, hc, hfo])
     fb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4)
     hb = random_pops(rng, rng.uniform(0.7, 1.3), 0.4) * 0.8
@@ -194,4 +197,5 @@ def test_kernel_equilibria_match_oracle_fp64(shim, seed):
     np.testing.assert_allclose(f, O.feq(rho, ux, uy, T / 3), atol=2e-15)
     if p.thermal:  # no energy DF in the athermal scheme
         shim.shim_heq(P(cst), P(ref), rho, ux, uy, T, P(h))
-        np.testing.assert_allclose(h, O.heq(rho, ux, uy, T / 3, cst[2], int(cst[11])), atol=3e-15)
+        want = O.geq(rho, ux, uy, T / 3, cst[2]) if p.energy_df else O.heq(rho, ux, uy, T / 3, cst[2], int(cst[11]))
+        np.testing.assert_allclose(h, want, atol=3e-15)
