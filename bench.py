@@ -404,7 +404,13 @@ def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=
         nus = out[storage].pop("_nu")
         if nu_fp32:
             e = [abs(nus[k] - nu_fp32[k]) / abs(nu_fp32[k]) for k in nus if k in nu_fp32]
-            out[storage]["nu_rel_err_vs_fp32_same_start"] = {"max": max(e) if e else None, "n": len(e)}
+            m = max(e) if e else None
+            # the 16-bit precision target: steady Nu within 5e-3 of the FP32
+            # run from the identical start (the FP32 run's own offset from the
+            # FP64 time average is the restart transient, the same in every
+            # storage form)
+            out[storage]["nu_rel_err_vs_fp32_same_start"] = {"max": m, "n": len(e),
+                                                             "meets_5e-3": (m < 5e-3) if m is not None else None}
     out["restart_length"] = "restart requests run 30 H/u_c from the FP64 steady fields"
     return out
 
