@@ -44,7 +44,9 @@ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // the "lowbias32" integer hash (C. Wellons' hash-prospector) of the node
 // index and the step; per plane, a multiplicative spread of that word.  The
 // result depends only on (step, node, plane), so it is the same for any
-// launch shape or batch composition.
+// launch shape or batch composition.  The per-plane spread multiplies the
+// low 24 bits (a full-rate multiply; a 32-bit one issues at a quarter of the
+// rate) and the encoders take the top bits of the product.
 __device__ __forceinline__ unsigned sr_node(unsigned node, unsigned step) {
   unsigned x = node ^ (step * 0x9E3779B9u);
   x ^= x >> 16;
@@ -55,7 +57,7 @@ __device__ __forceinline__ unsigned sr_node(unsigned node, unsigned step) {
   return x;
 }
 __device__ __forceinline__ unsigned sr_word(unsigned hn, int plane) {
-  return (hn ^ ((unsigned)plane * 0x632BE5ABu)) * 0x85EBCA6Bu;  // use the top bits
+  return __umul24(hn ^ ((unsigned)plane * 0x632BE5ABu), 0xEBCA6Bu);  // use the top bits
 }
 constexpr unsigned kInitStep = 0xFFFFFFFFu;  // generator step of the initial state
 
@@ -95,6 +97,17 @@ struct Store<kF16> {
   using T = unsigned short;
   static __device__ __forceinline__ float dec(T b) { return __half2float(__ushort_as_half(b)) * 0x1p-10f; }
   static __device__ __forceinline__ float ld(const T *p, long long i) { return dec(p[i]); }
+  // the pulls keep the loaded bits (zero-extended, in a float register) and
+  // decode them together with the row shift: one mixed-precision
+  // multiply-add, bits x 2^-10 + add
+  static __device__ __forceinline__ float ld_raw(const T *p, long long i) { return __uint_as_float(p[i]); }
+  static __device__ __forceinline__ float ldb_raw(__amdgpu_buffer_rsrc_t r, unsigned vb, unsigned sb) {
+    return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
+  }
+  static __device__ __forceinline__ float dec_add(float raw, float add) {
+    const _Float16 hv = __builtin_bit_cast(_Float16, (T)__float_as_uint(raw));
+    return __builtin_fmaf((float)hv, 0x1p-10f, add);
+  }
   static __device__ __forceinline__ void st(T *p, long long i, float v, unsigned rnd) { p[i] = enc(v, rnd); }
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, unsigned vb, unsigned sb) {
     return dec(__builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
@@ -115,6 +128,13 @@ struct Store<kBF16> {  // bfloat16: the upper half of the FP32 pattern, stochast
   using T = unsigned short;
   static __device__ __forceinline__ float dec(T b) { return __bfloat162float(__ushort_as_bfloat16(b)); }
   static __device__ __forceinline__ float ld(const T *p, long long i) { return dec(p[i]); }
+  static __device__ __forceinline__ float ld_raw(const T *p, long long i) { return __uint_as_float(p[i]); }
+  static __device__ __forceinline__ float ldb_raw(__amdgpu_buffer_rsrc_t r, unsigned vb, unsigned sb) {
+    return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
+  }
+  static __device__ __forceinline__ float dec_add(float raw, float add) {
+    return __uint_as_float(__float_as_uint(raw) << 16) + add;
+  }
   static __device__ __forceinline__ void st(T *p, long long i, float v, unsigned rnd) { p[i] = enc(v, rnd); }
   static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, unsigned vb, unsigned sb) {
     return dec(__builtin_amdgcn_raw_buffer_load_b16(r, vb, sb, 0));
@@ -327,6 +347,24 @@ __device__ __forceinline__ RowSrc row_src(const KParams &k, int y) {
 // (col.xc, y), f_a = P_a(x - e_a), as stored (deviations of the source row).
 // Links from outside a non-periodic side bounce back halfway at rest,
 // f_a = P_opp(a)(x).  Interior tiles and rows take a select-free path.
+// What a pull keeps in a register until pull_shift: the value (FP32, FP64),
+// or the loaded 16-bit pattern, which pull_shift decodes together with the
+// row shift.
+template <int S>
+struct Pull {
+  static constexpr bool kRaw = (S == kF16 || S == kBF16);
+  using R = typename Real<S>::T;
+  using ST = typename Store<S>::T;
+  static __device__ __forceinline__ R ld(const ST *p, long long i) {
+    if constexpr (kRaw) return Store<S>::ld_raw(p, i);
+    else return Store<S>::ld(p, i);
+  }
+  static __device__ __forceinline__ R ldb(__amdgpu_buffer_rsrc_t r, unsigned vb, unsigned sb) {
+    if constexpr (kRaw) return Store<S>::ldb_raw(r, vb, sb);
+    else return Store<S>::ldb(r, vb, sb);
+  }
+};
+
 template <int S, int M = 0>
 __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &col,
                                            typename Real<S>::T *f, typename Real<S>::T *h) {
@@ -343,8 +381,8 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
         const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
                              (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
         const unsigned vb = off * (unsigned)sizeof(ST);
-        f[a] = Store<S>::ldb(r, vb, plane_bytes<S>(k, a));
-        h[a] = Store<S>::ldb(r, vb, plane_bytes<S>(k, a + 9));
+        f[a] = Pull<S>::ldb(r, vb, plane_bytes<S>(k, a));
+        h[a] = Pull<S>::ldb(r, vb, plane_bytes<S>(k, a + 9));
       }
       return;
     }
@@ -360,8 +398,8 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
       const int pa = bb ? kOpp[a] : a;
       const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
       const unsigned vb = off * (unsigned)sizeof(ST);
-      f[a] = Store<S>::ldb(r, vb + plane_bytes<S>(k, pa), 0u);
-      h[a] = Store<S>::ldb(r, vb + plane_bytes<S>(k, pa + 9), 0u);
+      f[a] = Pull<S>::ldb(r, vb + plane_bytes<S>(k, pa), 0u);
+      h[a] = Pull<S>::ldb(r, vb + plane_bytes<S>(k, pa + 9), 0u);
     }
     return;
   }
@@ -371,8 +409,8 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
       const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
                            (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
       const ST *base = src + a * k.plane;
-      f[a] = Store<S>::ld(base, off);
-      if (flags<M>(k).thermal) h[a] = Store<S>::ld(base + hoff, off);
+      f[a] = Pull<S>::ld(base, off);
+      if (flags<M>(k).thermal) h[a] = Pull<S>::ld(base + hoff, off);
     }
     return;
   }
@@ -385,8 +423,8 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
     const bool bb = ox || oy;
     const ST *base = src + (bb ? kOpp[a] : a) * k.plane;
     const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
-    f[a] = Store<S>::ld(base, off);
-    if (flags<M>(k).thermal) h[a] = Store<S>::ld(base + hoff, off);
+    f[a] = Pull<S>::ld(base, off);
+    if (flags<M>(k).thermal) h[a] = Pull<S>::ld(base + hoff, off);
   }
 }
 
@@ -400,6 +438,33 @@ __device__ __forceinline__ void pull_shift(const KParams &k, int y, const Col &c
   const ConstPtr<R> shF = const_table<R>(k.shiftF) + 9 * y;
   const ConstPtr<R> shH = const_table<R>(k.shiftH) + 9 * y;
   const RowSrc rs = row_src(k, y);
+  const bool th = flags<M>(k).thermal;
+  if constexpr (Pull<S>::kRaw) {
+    // 16-bit patterns: decode every plane, adding the shift (wave-uniform
+    // unless the x ends bounce back, where it depends on the lane)
+    R af[9], ah[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const bool keep = kEy[a] != 0 && !(kEy[a] > 0 ? rs.outB : rs.outT);
+      af[a] = keep ? shF[a] : R(0);
+      ah[a] = (keep && th) ? shH[a] : R(0);
+    }
+    if (k.bc[kXlo] == kPeriodic) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        f[a] = Store<S>::dec_add(f[a], af[a]);
+        if (th) h[a] = Store<S>::dec_add(h[a], ah[a]);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
+        f[a] = Store<S>::dec_add(f[a], ox ? R(0) : af[a]);
+        if (th) h[a] = Store<S>::dec_add(h[a], ox ? R(0) : ah[a]);
+      }
+    }
+    return;
+  }
   // the table entries are read unconditionally (always in bounds) and applied
   // by selection, so that their loads are not tied to branches
 #pragma unroll
