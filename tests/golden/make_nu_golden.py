@@ -183,7 +183,7 @@ def main():
         with ProcessPoolExecutor(max_workers=int(os.environ.get("NU_WORKERS", "4"))) as ex:
             hist = list(ex.map(run_history, jobs))
         out = dict(workload="rb_table3: 2N x N, N 80/100/150, dT 0.06, u_c 0.08, Pr 0.71, internal-energy DF, "
-                            "seed 1, noise 1e-3", runs=[])
+                            "1e-3 density perturbation of the critical mode shape", runs=[])
         for c, (_, every, total, avg_from, _), h in zip(cases, jobs, hist):
             out["runs"].append(dict(Ra=c.meta["Ra"], nx=c.nx, ny=c.ny, every=every, total=total,
                                     avg_from=avg_from, **h))
