@@ -148,3 +148,45 @@ def test_table3_sweep(T):
         assert abs(nu - pn) / pn < 0.05
         assert nr == 2
     assert all(a < b for a, b in zip(nus, nus[1:]))
+
+
+def test_internal_energy_16bit_storage(T):
+    """The internal-energy DF with FP16 storage (the generic 16-bit
+    instantiation), RB 256 x 128 from near rest, 100 steps: rho and T within
+    the FP16 bound of their maxima and the perturbations within the FP16
+    perturbation bound of the total-energy path."""
+    from test_gpu_parity import PERT_TOL_16
+    case = W.rayleigh_benard(nx=256, ny=128, Ra=1e4, Pr=0.71, dT=0.06, seed=4, noise=1e-3).with_(energy_df=1)
+    say("case internal-energy rayleigh-benard 256x128 f16 storage 100 steps")
+    g, o = _pair(T, case, 100, "f16")
+    e, p = rel_err(g, o, case), pert_err(g, o, case)
+    say(f"  errors {e}; perturbation errors {p}")
+    assert max(e["rho"], e["T"]) < 2e-3
+    assert max(p.values()) < PERT_TOL_16["f16"]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_mixed_batch_equals_members_alone(T, storage):
+    """A batch whose members run the internal-energy DF and the default
+    total-energy DF side by side (the batch kernel picks the scheme per
+    member) leaves every member bitwise where it would be alone."""
+    import torch
+    cases = [W.rayleigh_benard(nx=130, ny=67, Ra=1e4, Pr=0.71, dT=0.06, seed=5, noise=1e-3).with_(energy_df=1),
+             W.rayleigh_benard(nx=200, ny=41, Ra=2e4, Pr=0.71, seed=6, noise=1e-3),
+             W.couette(u0=0.05, w2=1.0, w3=1.0, w4=1.0).with_(energy_df=1)]
+    say(f"case mixed batch {storage}: internal-energy and total-energy members, 53 steps")
+    stream = torch.cuda.Stream()
+    alone = []
+    for c in cases:
+        lat = T.Lattice(c, storage=storage, stream=stream)
+        lat.step(53)
+        alone.append(lat.read_state())
+        lat.close()
+    lats = [T.Lattice(c, storage=storage, stream=stream) for c in cases]
+    b = T.Batch(lats)
+    b.set_graph_chunk(16)
+    b.step(53)
+    b.close()
+    for k, lat in enumerate(lats):
+        assert np.array_equal(lat.read_state(), alone[k]), k
+        lat.close()
