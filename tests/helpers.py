@@ -45,3 +45,37 @@ def random_pops(rng, rho=1.0, spread=0.2):
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
     f = w * (1.0 + spread * rng.uniform(-1, 1, 9))
     return rho * f / f.sum()
+
+
+def taylor_green_e2(N, u0, max_blocks=400, rates=None, threads=None):
+    """E2 of the oracle's steady forced Taylor-Green flow (Section 5A) at the
+    paper's convergence criterion, E_R < 1e-8 over 1000 steps.  Module-level
+    so that worker processes can run several amplitudes side by side."""
+    from paper_1610_07114_amd import workloads as W
+    if threads:
+        O.set_num_threads(threads)
+    case = W.taylor_green(N=N, u0=u0)
+    if rates:
+        case = case.with_(w2=rates[0], w3=rates[1], w4=rates[2])
+    L = oracle_lattice(case)
+    prev = None
+    for _ in range(max_blocks):
+        L.step(1000)
+        _, ux, uy, _ = L.macros()
+        if prev is not None:
+            ER = np.sqrt(((ux - prev[0]) ** 2 + (uy - prev[1]) ** 2).sum() / (ux ** 2 + uy ** 2).sum())
+            if ER < 1e-8:
+                break
+        prev = (ux, uy)
+    ue, ve = case.meta["ux_exact"], case.meta["uy_exact"]
+    return float(np.sqrt(((ux - ue) ** 2 + (uy - ve) ** 2).sum() / (ue ** 2 + ve ** 2).sum()))
+
+
+def couette_mu_T_fields(Pr, gamma, steps=60000, threads=None, **over):
+    """Fields (rho, ux, uy, T) of the Section 5B Couette case with
+    mu = mu0 T/T0 after `steps` steps, with oracle option overrides."""
+    from paper_1610_07114_amd import workloads as W
+    if threads:
+        O.set_num_threads(threads)
+    case = W.couette_variable_viscosity(Pr=Pr, gamma=gamma)
+    return oracle_lattice(case, **over).step(steps).macros()

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import riemann
-from helpers import oracle_lattice, oracle_params
+from helpers import oracle_lattice, oracle_params, taylor_green_e2
 from paper_1610_07114_amd import workloads as W
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -28,28 +28,25 @@ def _load_table1():
 
 
 def _run_taylor_green(N, u0, max_blocks=400, rates=None):
-    case = W.taylor_green(N=N, u0=u0)
-    if rates:
-        case = case.with_(w2=rates[0], w3=rates[1], w4=rates[2])
-    L = oracle_lattice(case)
-    prev = None
-    for _ in range(max_blocks):
-        L.step(1000)
-        _, ux, uy, _ = L.macros()
-        if prev is not None:
-            ER = np.sqrt(((ux - prev[0]) ** 2 + (uy - prev[1]) ** 2).sum() / (ux ** 2 + uy ** 2).sum())
-            if ER < 1e-8:
-                break
-        prev = (ux, uy)
-    ue, ve = case.meta["ux_exact"], case.meta["uy_exact"]
-    return np.sqrt(((ux - ue) ** 2 + (uy - ve) ** 2).sum() / (ue ** 2 + ve ** 2).sum())
+    return taylor_green_e2(N, u0, max_blocks, rates)
+
+
+@pytest.fixture(scope="module")
+def table1_e2():
+    """The four Table 1 runs (64 x 64 to convergence) side by side in worker
+    processes: a 64 x 64 lattice gains little from threads."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    rows = _load_table1()
+    with ProcessPoolExecutor(max_workers=len(rows), mp_context=mp.get_context("spawn")) as ex:
+        futs = {u0: ex.submit(taylor_green_e2, 64, u0, 400, None, 2) for u0, _ in rows}
+        return {u0: f.result() for u0, f in futs.items()}
 
 
 @pytest.mark.parametrize("u0,e2_paper", _load_table1())
-def test_taylor_green_table1(u0, e2_paper):
+def test_taylor_green_table1(table1_e2, u0, e2_paper):
     """Table 1, row 'Present': E2 at N = 64 for four forcing amplitudes."""
-    e2 = _run_taylor_green(64, u0)
-    assert e2 == pytest.approx(e2_paper, rel=0.01)
+    assert table1_e2[u0] == pytest.approx(e2_paper, rel=0.01)
 
 
 def _load_table2():
