@@ -415,6 +415,52 @@ def bench_serving(torch, tclbm, n_requests=500, storages=("f16",), seed=0, load=
     return out
 
 
+def bench_table3(torch, tclbm):
+    """Section 5D's Nu(Ra) sweep with the internal-energy DF: the five Table 3
+    lattices (2N x N, N = 80/100/150) as one FP32 batch from the critical-mode
+    start, 100 flow times (150 at Ra 2500), Nu averaged over the last 10 flow
+    times, against the printed values."""
+    import numpy as np
+    from paper_1610_07114_amd import serving as S
+    from paper_1610_07114_amd import workloads as W
+    cases = [W.rb_table3(Ra) for Ra in W.TABLE3_RA]
+    sched = []
+    for c in cases:
+        tu = c.meta["H"] / c.meta["uc"]
+        every = max(1, int(round(tu / 4)))
+        total = int(round((150.0 if c.meta["Ra"] < 3000 else 100.0) * tu / every)) * every
+        sched.append((every, total, total - int(round(10.0 * tu / every)) * every))
+    stream = torch.cuda.Stream()
+    lats = [tclbm.Lattice(c, storage="f32", stream=stream) for c in cases]
+    b = tclbm.Batch(lats)
+    b.set_graph_chunk(16)
+    points = sorted({p for ev, tot, _ in sched for p in range(ev, tot + 1, ev)})
+    samples = [[] for _ in cases]
+    t0 = time.perf_counter()
+    done = 0
+    for p in points:
+        b.step(p - done)
+        done = p
+        for k, (c, lat, (ev, tot, frm)) in enumerate(zip(cases, lats, sched)):
+            if p % ev == 0 and frm < p <= tot:
+                _, _, _, _, sm = lat.moments(fields=False)
+                samples[k].append(S.nusselt_from_sums(c, sm))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.close()
+    for lat in lats:
+        lat.close()
+    out = {"workload": "rb_table3: 2N x N, N 80/100/150, dT 0.06, u_c 0.08, Pr 0.71, internal-energy DF, "
+                       "FP32 batch of the five", "steps": done, "wall_s": round(wall, 2),
+           "mlups": round(sum(c.nx * c.ny for c in cases) * done / wall / 1e6, 1), "nu": {}}
+    for c, smp in zip(cases, samples):
+        nu = float(np.mean(smp))
+        pn, pref = W.TABLE3_NU[c.meta["Ra"]]
+        out["nu"][f"{c.meta['Ra']:g}"] = {"nu": round(nu, 5), "paper": pn, "reference": pref,
+                                           "rel_vs_paper": round(nu / pn - 1.0, 4)}
+    return out
+
+
 def single_extra(torch, tclbm, name, storage, steps, warmup, traffic_json, reduce_every=1000):
     """A single-lattice figure measured beside the headline: MLUPS over `steps`
     steps (FP64 sums every `reduce_every`) and the roofline of its kernel."""
@@ -506,6 +552,8 @@ def main():
             for st in ("f32", "f16", "bf16"):
                 log(f"bench: RB 8192x4096 {st}, 200 warmup + 1000 timed steps")
                 out["roofline_large"][st] = single_extra(torch, tclbm, "large", st, 1000, 200, args.traffic_json)
+            log("bench: Section 5D Table 3 sweep, internal-energy DF, FP32 batch of five lattices")
+            out["table3"] = bench_table3(torch, tclbm)
             log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
             ceil = copy_probe(torch, tclbm)
             out["hbm_ceiling"] = ceil

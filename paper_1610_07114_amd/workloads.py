@@ -178,6 +178,9 @@ def rayleigh_benard(nx: int = 512, ny: int = 256, Ra: float = 1e5, Pr: float = 0
 
 
 TABLE3_RA = (2500.0, 5000.0, 10000.0, 30000.0, 50000.0)
+# Nu printed in Section 5D, Table 3: (the paper's scheme, the reference solution)
+TABLE3_NU = {2500.0: (1.468, 1.475), 5000.0: (2.106, 2.116), 10000.0: (2.650, 2.661),
+             30000.0: (3.629, 3.662), 50000.0: (4.181, 4.245)}
 
 
 def rb_table3(Ra: float) -> Case:
