@@ -7,8 +7,10 @@
  * density DF f, relaxed by the cascaded (central-moment) collision with
  * central-moment forcing (Sections 2-3) and the third-moment correction term
  * C (Section 4), and the total-energy DF h, relaxed towards its equilibrium
- * with the coupling source K (Section 4).  Both are pull-streamed.  Every step
- * is one fused HIP kernel launch on the handle's stream.
+ * with the coupling source K (Section 4) -- or, for the Rayleigh-Benard runs
+ * of Section 5D, an internal-energy DF (tclbm_params.energy_df).  Both are
+ * pull-streamed.  Every step is one fused HIP kernel launch on the handle's
+ * stream.
  *
  * Conventions
  *   - Lattice units: R*T0 must be 1/3 (c_s^2); the default R = 1/3, T0 = 1.
@@ -142,7 +144,7 @@ typedef struct {
 typedef struct {
   double mass;       /* sum rho */
   double momx, momy; /* sum rho u */
-  double energy;     /* sum of hbar = sum rho E */
+  double energy;     /* sum of hbar = sum rho E (sum rho e with energy_df = 1) */
   double kinetic;    /* sum rho u^2 / 2 */
   double nu_num;     /* sum u_y (T - T0)  (Nusselt numerator, Section 5D) */
   double rho_min, T_min;
@@ -160,7 +162,8 @@ void tclbm_default_params(int32_t nx, int32_t ny, tclbm_params *p);
 size_t tclbm_state_bytes(const tclbm_params *p);
 
 /* Validate p, lay out dev_buf, upload the initial macroscopic fields and
- * initialise fbar = f^eq - S/2, hbar = h^eq (Sections 3-4) on the stream.
+ * initialise fbar = f^eq - S/2, hbar = h^eq (Sections 3-4; g^eq = e f^eq for
+ * the internal-energy DF) on the stream.
  * rho, ux, uy, T: host, nx*ny each (T ignored when thermal = 0).
  * ax_field, ay_field: host per-node acceleration (nullable; when given they
  * replace the uniform ax, ay).  hip_stream: a hipStream_t (NULL: default).
@@ -195,7 +198,8 @@ tclbm_status tclbm_set_bc(tclbm_handle h, int32_t side, int32_t kind, double ux_
  * Eq. (3), the energy-DF update of Section 4 with its coupling source K, and
  * pull streaming of both DFs: Eq. (27) for f and the time-discrete energy-DF
  * equation of Section 4 for h.  The reading of the energy-DF update
- * (heq_moments, h_collision, h_force) follows the parameters.  Long runs replay
+ * (heq_moments, h_collision, h_force, or the internal-energy DF of Section
+ * 5D with energy_df = 1) follows the parameters.  Long runs replay
  * a captured HIP graph of a fixed chunk of steps (not on the NULL stream, which
  * cannot be captured).  nsteps >= 0.  E_INVALID for a NULL handle, nsteps < 0
  * or an unpaired periodic axis; E_STATE once the handle has reported an
