@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
@@ -60,8 +61,8 @@ bool valid_params(const tclbm_params *p) {
   if (!p) return false;
   if (p->nx < 3 || p->ny < 3) return false;
   if ((long long)p->nx * p->ny > (1LL << 28)) return false;
-  // kernels index within a population plane with 32-bit element offsets
-  if (up((size_t)p->nx, 64) * (size_t)p->ny >= (1ULL << 32)) return false;
+  // kernels index a state buffer (all of its planes) with 32-bit element offsets
+  if (up((size_t)p->nx, 64) * (size_t)p->ny * (size_t)(p->thermal ? 18 : 9) >= (1ULL << 32)) return false;
   if (!(std::isfinite(p->R) && std::isfinite(p->T0) && p->R > 0 && p->T0 > 0)) return false;
   if (std::fabs(p->R * p->T0 - 1.0 / 3.0) > 1e-12) return false;
   if (!(p->gamma > 1.0) || !(p->Pr > 0.0) || !std::isfinite(p->gamma) || !std::isfinite(p->Pr)) return false;
@@ -125,6 +126,22 @@ void fill_kparams(tclbm_ctx *c) {
   k.ny = p.ny;
   k.pitch = pitch_of(&p);
   k.plane = (long long)k.pitch * p.ny;
+  // state layout (tclbm_internal.h): tile-interleaved unless
+  // TCLBM_PLANE_MAJOR=1 asks for one plane after the other
+  const int np = planes_of(&p);
+  static const bool plane_major = [] {
+    const char *e = getenv("TCLBM_PLANE_MAJOR");
+    return e && atoi(e) == 1;
+  }();
+  if (plane_major) {
+    k.pstride = k.plane;
+    k.tstride = 64;
+    k.rstride = (unsigned)k.pitch;
+  } else {
+    k.pstride = 64;
+    k.tstride = np * 64;
+    k.rstride = (unsigned)np * (unsigned)k.pitch;
+  }
   k.thermal = p.thermal;
   k.correction = p.correction;
   k.heq_mode = p.heq_moments;

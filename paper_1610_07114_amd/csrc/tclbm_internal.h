@@ -21,8 +21,16 @@ struct KParams {
   const void *src;  // population buffer read this step (storage type)
   void *dst;        // population buffer written this step
   int nx, ny;
-  int pitch;        // elements per stored row (>= nx)
-  long long plane;  // elements per population plane (pitch * ny)
+  int pitch;        // columns per stored row (nx rounded up to 64)
+  long long plane;  // nodes per population plane (pitch * ny); the buffer holds 9 or 18 planes
+  // Element strides of the state layout: population a of node (x, y) sits at
+  // y * rstride + (x >> 6) * tstride + a * pstride + (x & 63).  Tile-
+  // interleaved (default): the planes of one 64-column block of a row are
+  // contiguous, pstride = 64, tstride = planes * 64, rstride = planes * pitch.
+  // Plane-major: pstride = plane, tstride = 64, rstride = pitch.
+  long long pstride;
+  int tstride;
+  unsigned rstride;
   int thermal, correction, heq_mode, h_coll, h_force, wall_rho;
   int visc_mode;  // 1: per-node rates from mu = mu0 T/T0 (mu0 here as mu0/(R T0))
   double mu0_RT0, Pr;

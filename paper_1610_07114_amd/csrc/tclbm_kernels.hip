@@ -244,8 +244,15 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 struct Col {
   int xc;         // column whose node this lane evaluates
   int xm, xp;     // source columns of links with e_x = +1 / -1
+  unsigned oc, om, op;  // their element offsets within a stored row (state layout)
   bool outL, outR;  // those links come from outside (non-periodic x)
 };
+
+// Element offset of column x within a stored row of the state (see
+// KParams::pstride): 64-column blocks of tstride elements.
+__device__ __forceinline__ unsigned col_off(const KParams &k, int x) {
+  return (unsigned)(x >> 6) * (unsigned)k.tstride + (unsigned)(x & 63);
+}
 
 __device__ __forceinline__ Col make_col(const KParams &k, int xl) {
   Col c;
@@ -265,6 +272,9 @@ __device__ __forceinline__ Col make_col(const KParams &k, int xl) {
     c.xm = c.outL ? x : x - 1;
     c.xp = c.outR ? x : x + 1;
   }
+  c.oc = col_off(k, c.xc);
+  c.om = col_off(k, c.xm);
+  c.op = col_off(k, c.xp);
   return c;
 }
 
@@ -305,7 +315,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const void *p, cons
 }
 template <int S>
 __device__ __forceinline__ unsigned plane_bytes(const KParams &k, int a) {
-  return (unsigned)((unsigned long long)a * (unsigned long long)k.plane * sizeof(typename Store<S>::T));
+  return (unsigned)((unsigned long long)a * (unsigned long long)k.pstride * sizeof(typename Store<S>::T));
 }
 
 template <class R>
@@ -337,9 +347,9 @@ __device__ __forceinline__ RowSrc row_src(const KParams &k, int y) {
     ym = r.outB ? y : y - 1;
     yp = r.outT ? y : y + 1;
   }
-  r.rm = (unsigned)ym * k.pitch;
-  r.rc = (unsigned)y * k.pitch;
-  r.rp = (unsigned)yp * k.pitch;
+  r.rm = (unsigned)ym * k.rstride;
+  r.rc = (unsigned)y * k.rstride;
+  r.rp = (unsigned)yp * k.rstride;
   return r;
 }
 
@@ -371,7 +381,7 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
   using ST = typename Store<S>::T;
   const ST *src = reinterpret_cast<const ST *>(k.src);
   const RowSrc rs = row_src(k, y);
-  const long long hoff = 9 * k.plane;
+  const long long hoff = 9 * k.pstride;
   if constexpr (M == 2) {
     // all offsets are non-negative and inside the buffer
     const __amdgpu_buffer_rsrc_t r = state_rsrc<S>(k.src, k);
@@ -379,7 +389,7 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
-                             (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
+                             (kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc));
         const unsigned vb = off * (unsigned)sizeof(ST);
         f[a] = Pull<S>::ldb(r, vb, plane_bytes<S>(k, a));
         h[a] = Pull<S>::ldb(r, vb, plane_bytes<S>(k, a + 9));
@@ -390,13 +400,13 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
     // plane may differ per lane, so it goes into the lane's byte offset
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+      const unsigned sx = kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc);
       const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
       const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
       const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
       const bool bb = ox || oy;
       const int pa = bb ? kOpp[a] : a;
-      const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
+      const unsigned off = bb ? rs.rc + col.oc : sr + sx;
       const unsigned vb = off * (unsigned)sizeof(ST);
       f[a] = Pull<S>::ldb(r, vb + plane_bytes<S>(k, pa), 0u);
       h[a] = Pull<S>::ldb(r, vb + plane_bytes<S>(k, pa + 9), 0u);
@@ -407,8 +417,8 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
-                           (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
-      const ST *base = src + a * k.plane;
+                           (kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc));
+      const ST *base = src + a * k.pstride;
       f[a] = Pull<S>::ld(base, off);
       if (flags<M>(k).thermal) h[a] = Pull<S>::ld(base + hoff, off);
     }
@@ -416,13 +426,13 @@ __device__ __forceinline__ void pull_issue(const KParams &k, int y, const Col &c
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+    const unsigned sx = kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc);
     const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
     const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
     const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
     const bool bb = ox || oy;
-    const ST *base = src + (bb ? kOpp[a] : a) * k.plane;
-    const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
+    const ST *base = src + (bb ? kOpp[a] : a) * k.pstride;
+    const unsigned off = bb ? rs.rc + col.oc : sr + sx;
     f[a] = Pull<S>::ld(base, off);
     if (flags<M>(k).thermal) h[a] = Pull<S>::ld(base + hoff, off);
   }
@@ -511,7 +521,7 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
     // offset; bounce-back links carry their plane in the lane's offset
     const __amdgpu_buffer_rsrc_t r = state_rsrc<kF32>(k.src, k);
     if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
-      const unsigned cm = (unsigned)col.xm * 4u, cz = (unsigned)col.xc * 4u, cp = (unsigned)col.xp * 4u;
+      const unsigned cm = col.om * 4u, cz = col.oc * 4u, cp = col.op * 4u;
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         const unsigned rb = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) * 4u;
@@ -524,27 +534,27 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+      const unsigned sx = kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc);
       const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
       const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
       const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
       const bool bb = ox || oy;
       const int pa = bb ? kOpp[a] : a;
-      const unsigned vb = (bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx) * 4u + plane_bytes<kF32>(k, pa);
+      const unsigned vb = (bb ? rs.rc + col.oc : sr + sx) * 4u + plane_bytes<kF32>(k, pa);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + a * 64), 4, vb, 0u, 0, 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (LV *)(slot + (9 + a) * 64), 4, vb + plane_bytes<kF32>(k, 9), 0u,
                                                0, 0);
     }
     return;
   }
-  const long long hoff = 9 * k.plane;
+  const long long hoff = 9 * k.pstride;
   const bool th = flags<M>(k).thermal;
   if (k.bc[kXlo] == kPeriodic && !rs.outB && !rs.outT) {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       const unsigned off = (kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc)) +
-                           (unsigned)(kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc));
-      const float *base = src + a * k.plane;
+                           (kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc));
+      const float *base = src + a * k.pstride;
       __builtin_amdgcn_global_load_lds((GV *)(base + off), (LV *)(slot + a * 64), 4, 0, 0);
       if (th) __builtin_amdgcn_global_load_lds((GV *)(base + hoff + off), (LV *)(slot + (9 + a) * 64), 4, 0, 0);
     }
@@ -552,13 +562,13 @@ __device__ __forceinline__ void pull_issue_lds(const KParams &k, int y, const Co
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    const int sx = kEx[a] > 0 ? col.xm : (kEx[a] < 0 ? col.xp : col.xc);
+    const unsigned sx = kEx[a] > 0 ? col.om : (kEx[a] < 0 ? col.op : col.oc);
     const bool ox = kEx[a] > 0 ? col.outL : (kEx[a] < 0 ? col.outR : false);
     const unsigned sr = kEy[a] > 0 ? rs.rm : (kEy[a] < 0 ? rs.rp : rs.rc);
     const bool oy = kEy[a] > 0 ? rs.outB : (kEy[a] < 0 ? rs.outT : false);
     const bool bb = ox || oy;
-    const float *base = src + (bb ? kOpp[a] : a) * k.plane;
-    const unsigned off = bb ? rs.rc + (unsigned)col.xc : sr + (unsigned)sx;
+    const float *base = src + (bb ? kOpp[a] : a) * k.pstride;
+    const unsigned off = bb ? rs.rc + col.oc : sr + sx;
     __builtin_amdgcn_global_load_lds((GV *)(base + off), (LV *)(slot + a * 64), 4, 0, 0);
     if (th) __builtin_amdgcn_global_load_lds((GV *)(base + hoff + off), (LV *)(slot + (9 + a) * 64), 4, 0, 0);
   }
@@ -748,13 +758,16 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   collide<R, (S == kF32 || S == kF64)>(cn, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
   if (!store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
-  const unsigned own = (unsigned)y * k.pitch + (unsigned)col.xc;
-  const unsigned hn = (S == kF16 || S == kBF16) ? sr_node(own, step) : 0u;
+  // the node's number (y * pitch + x) keys the rounding generator; its
+  // address follows the state layout
+  const unsigned node = (unsigned)y * k.pitch + (unsigned)col.xc;
+  const unsigned hn = (S == kF16 || S == kBF16) ? sr_node(node, step) : 0u;
+  const unsigned own = (unsigned)y * k.rstride + col.oc;
   if constexpr (M == 2) {
     // row and plane in the scalar offset, the column in the vector offset
     const __amdgpu_buffer_rsrc_t r = state_rsrc<S>(k.dst, k);
-    const unsigned vb = (unsigned)col.xc * (unsigned)sizeof(ST);
-    const unsigned rb = (unsigned)y * (unsigned)k.pitch * (unsigned)sizeof(ST);
+    const unsigned vb = col.oc * (unsigned)sizeof(ST);
+    const unsigned rb = (unsigned)y * k.rstride * (unsigned)sizeof(ST);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       Store<S>::stb(r, vb, plane_bytes<S>(k, a) + rb, P[a], sr_word(hn, a));
@@ -764,8 +777,8 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    (dst + a * k.plane)[own] = Store<S>::enc(P[a], sr_word(hn, a));
-    if (flags<M>(k).thermal) (dst + (a + 9) * k.plane)[own] = Store<S>::enc(Q[a], sr_word(hn, a + 9));
+    (dst + a * k.pstride)[own] = Store<S>::enc(P[a], sr_word(hn, a));
+    if (flags<M>(k).thermal) (dst + (a + 9) * k.pstride)[own] = Store<S>::enc(Q[a], sr_word(hn, a + 9));
   }
 }
 
@@ -1266,7 +1279,8 @@ __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho,
   const Consts<R> c = make_consts<R>(k);
   const bool xper = k.bc[kXlo] == kPeriodic, yper = k.bc[kYlo] == kPeriodic;
   ST *dst = reinterpret_cast<ST *>(k.dst);
-  const long long own = (long long)y * k.pitch + x;
+  const long long own = (long long)y * k.pitch + x;  // node number (rounding generator key)
+  const long long at = (long long)y * k.rstride + col_off(k, x);  // its address in the state layout
 #pragma unroll 1
   for (int a = 0; a < 9; ++a) {
     int tx = x + kEx[a], ty = y + kEy[a];
@@ -1302,12 +1316,12 @@ __global__ __launch_bounds__(256) void init_kernel(KParams k, const double *rho,
       shh = reinterpret_cast<const R *>(k.shiftH)[9 * ty + a];
     }
     const unsigned hn = sr_node((unsigned)own, kInitStep);
-    Store<S>::st(dst, (long long)a * k.plane + own, fe[comp] - R(0.5) * se[comp] - shf, sr_word(hn, a));
+    Store<S>::st(dst, (long long)a * k.pstride + at, fe[comp] - R(0.5) * se[comp] - shf, sr_word(hn, a));
     if (k.thermal) {
       const R E = R(0.5) * (c.b * th + vx * vx + vy * vy);
       const R sg = drho * E + q.rho * (R(0.5) * c.b * dth + R(0.5) * (vx * vx + vy * vy));
       heq_dev(c, q, drho, vx, vy, dth, sg, he);
-      Store<S>::st(dst, (long long)(a + 9) * k.plane + own, he[comp] - shh, sr_word(hn, a + 9));
+      Store<S>::st(dst, (long long)(a + 9) * k.pstride + at, he[comp] - shh, sr_word(hn, a + 9));
     }
   }
 }
@@ -1454,7 +1468,7 @@ __global__ __launch_bounds__(256) void read_state_kernel(KParams k, double *out)
   double r[9], s[9];
   ref_pops<double>(q, k.thermal, k.heq_mode, r, s);
   const double ref = (a < 9) ? r[a] : s[a - 9];
-  out[i] = ref + (double)Store<S>::ld(src, (long long)a * k.plane + (long long)y * k.pitch + x);
+  out[i] = ref + (double)Store<S>::ld(src, (long long)a * k.pstride + (long long)y * k.rstride + col_off(k, x));
 }
 
 hipError_t launch_read_state(const KParams &k, int storage, double *d_out, hipStream_t s) {
