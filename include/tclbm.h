@@ -90,7 +90,10 @@ typedef enum {
 } tclbm_bc_kind;
 
 typedef struct {
-  int32_t nx, ny;        /* lattice size, each >= 3 */
+  int32_t nx, ny;        /* lattice size, each >= 3; nx * ny <= 2^28 and
+                            round_up(nx, 64) * ny * planes < 2^32 (planes =
+                            18, or 9 when athermal: offsets within a state
+                            buffer are 32-bit), so up to about 238 M nodes */
   double R, T0;          /* gas constant and reference temperature, R*T0 = 1/3 */
   double gamma, Pr;      /* specific-heat ratio (> 1) and Prandtl number (> 0) */
   double tau_f;          /* 1/w1 (> 0.5): mu = p (tau_f - 1/2), Eq. (29) */
