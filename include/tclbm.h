@@ -91,9 +91,12 @@ typedef enum {
 
 typedef struct {
   int32_t nx, ny;        /* lattice size, each >= 3; nx * ny <= 2^28 and
-                            round_up(nx, 64) * ny * planes < 2^32 (planes =
-                            18, or 9 when athermal: offsets within a state
-                            buffer are 32-bit), so up to about 238 M nodes */
+                            ceil(nx / w) * 64 * ny * planes < 2^32, where
+                            w = 62 with periodic x, 61 otherwise (each x
+                            tile of w columns owns a 64-slot block per row)
+                            and planes = 18, or 9 when athermal (offsets
+                            within a state buffer are 32-bit): up to about
+                            230 M nodes */
   double R, T0;          /* gas constant and reference temperature, R*T0 = 1/3 */
   double gamma, Pr;      /* specific-heat ratio (> 1) and Prandtl number (> 0) */
   double tau_f;          /* 1/w1 (> 0.5): mu = p (tau_f - 1/2), Eq. (29) */
@@ -186,8 +189,10 @@ tclbm_status tclbm_create(const tclbm_params *p, void *dev_buf, size_t dev_bytes
  * uy_w, T_w: the imposed wall velocity and temperature (used by WALL; T_w > 0;
  * WALL_ADIABATIC takes its temperature from the fluid, BOUNCEBACK and
  * PERIODIC ignore all three).  E_INVALID for an unknown side or kind, a WALL
- * kind on an x side, an adiabatic wall with ny < 4 or a non-finite value
- * (nothing is changed then); an unpaired periodic axis is refused at step
+ * kind on an x side, an adiabatic wall with ny < 4, a non-finite value, or a
+ * change of an x side to or from PERIODIC (the x tiling of the state, hence
+ * its layout, is fixed by the x sides given at create) (nothing is changed
+ * then); an unpaired periodic axis is refused at step
  * time (set both sides of an axis before stepping).  Does not touch the
  * device; a batch that holds the handle must be rebuilt. */
 tclbm_status tclbm_set_bc(tclbm_handle h, int32_t side, int32_t kind, double ux_w, double uy_w, double T_w);

@@ -62,7 +62,11 @@ bool valid_params(const tclbm_params *p) {
   if (p->nx < 3 || p->ny < 3) return false;
   if ((long long)p->nx * p->ny > (1LL << 28)) return false;
   // kernels index a state buffer (all of its planes) with 32-bit element offsets
-  if (up((size_t)p->nx, 64) * (size_t)p->ny * (size_t)(p->thermal ? 18 : 9) >= (1ULL << 32)) return false;
+  {
+    const size_t tw = (p->bc[kXlo] == kPeriodic) ? 62 : 61;  // tile_w_of
+    if ((((size_t)p->nx + tw - 1) / tw) * 64 * (size_t)p->ny * (size_t)(p->thermal ? 18 : 9) >= (1ULL << 32))
+      return false;
+  }
   if (!(std::isfinite(p->R) && std::isfinite(p->T0) && p->R > 0 && p->T0 > 0)) return false;
   if (std::fabs(p->R * p->T0 - 1.0 / 3.0) > 1e-12) return false;
   if (!(p->gamma > 1.0) || !(p->Pr > 0.0) || !std::isfinite(p->gamma) || !std::isfinite(p->Pr)) return false;
@@ -96,6 +100,15 @@ bool valid_params(const tclbm_params *p) {
 
 int pitch_of(const tclbm_params *p) { return (int)up((size_t)p->nx, 64); }
 int planes_of(const tclbm_params *p) { return p->thermal ? 18 : 9; }
+// x tiling of the waves and of the state blocks: a wave covers 64 lanes,
+// lane_off halo lanes on the left, tile_w columns it evaluates and stores
+// (62 with periodic x; 61 otherwise, for the second left neighbour that the
+// one-sided difference at the right edge needs)
+int lane_off_of(const tclbm_params *p) { return p->bc[kXlo] == kPeriodic ? 1 : 2; }
+int tile_w_of(const tclbm_params *p) { return 63 - lane_off_of(p); }
+// 64-slot blocks per stored row (one per x tile) and slots per plane
+size_t blocks_of(const tclbm_params *p) { return ((size_t)p->nx + tile_w_of(p) - 1) / tile_w_of(p); }
+size_t slots_of(const tclbm_params *p) { return blocks_of(p) * 64 * (size_t)p->ny; }
 
 struct Plan {
   size_t buf, ref, acc, part, ctr, total;
@@ -105,7 +118,7 @@ Plan plan_of(const tclbm_params *p) {
   Plan pl;
   const size_t esz = store_bytes(p->storage);
   const size_t plane = (size_t)pitch_of(p) * p->ny;
-  pl.buf = up(plane * planes_of(p) * esz, kAlign);
+  pl.buf = up(slots_of(p) * planes_of(p) * esz, kAlign);
   const size_t rsz = (p->storage == kF64) ? 8 : 4;
   pl.ref = up(rsz * (2 + 2 * 9) * (size_t)p->ny, kAlign);
   pl.acc = p->accel_field ? up(2 * plane * rsz, kAlign) : 0;
@@ -126,22 +139,15 @@ void fill_kparams(tclbm_ctx *c) {
   k.ny = p.ny;
   k.pitch = pitch_of(&p);
   k.plane = (long long)k.pitch * p.ny;
-  // state layout (tclbm_internal.h): tile-interleaved unless
-  // TCLBM_PLANE_MAJOR=1 asks for one plane after the other
+  // state layout (tclbm_internal.h): one 64-slot block per x tile and plane,
+  // the planes of a tile row contiguous
   const int np = planes_of(&p);
-  static const bool plane_major = [] {
-    const char *e = getenv("TCLBM_PLANE_MAJOR");
-    return e && atoi(e) == 1;
-  }();
-  if (plane_major) {
-    k.pstride = k.plane;
-    k.tstride = 64;
-    k.rstride = (unsigned)k.pitch;
-  } else {
-    k.pstride = 64;
-    k.tstride = np * 64;
-    k.rstride = (unsigned)np * (unsigned)k.pitch;
-  }
+  k.lane_off = lane_off_of(&p);
+  k.tile_w = tile_w_of(&p);
+  k.slots = (long long)slots_of(&p);
+  k.pstride = 64;
+  k.tstride = np * 64;
+  k.rstride = (unsigned)(np * 64 * blocks_of(&p));
   k.thermal = p.thermal;
   k.correction = p.correction;
   k.heq_mode = p.heq_moments;
@@ -185,9 +191,7 @@ static long long strip_target(int storage) {
 
 void decompose(tclbm_ctx *c) {
   KParams &k = c->k;
-  const bool xper = k.bc[kXlo] == kPeriodic;
-  k.lane_off = xper ? 1 : 2;
-  k.tile_w = 64 - 1 - k.lane_off;
+  // lane_off and tile_w are fixed at create with the state layout
   k.n_xtiles = (k.nx + k.tile_w - 1) / k.tile_w;
   int rows = c->strip_rows_req;
   if (rows <= 0) {
@@ -544,6 +548,10 @@ tclbm_status tclbm_set_bc(tclbm_handle c, int32_t side, int32_t kind, double ux_
   }
   if (!(std::isfinite(ux_w) && std::isfinite(uy_w) && std::isfinite(T_w)) || (kind == kWall && !(T_w > 0)))
     return TCLBM_E_INVALID;
+  if (side < kYlo && (kind == kPeriodic) != (c->p.bc[kXlo] == kPeriodic)) {
+    set_err(c, "x periodicity is fixed at create (the state layout depends on it)");
+    return TCLBM_E_INVALID;
+  }
   c->k.bc[side] = kind;
   c->k.wall_ux[side] = ux_w;
   c->k.wall_uy[side] = uy_w;

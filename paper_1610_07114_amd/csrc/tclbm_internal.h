@@ -23,11 +23,14 @@ struct KParams {
   int nx, ny;
   int pitch;        // columns per stored row (nx rounded up to 64)
   long long plane;  // nodes per population plane (pitch * ny); the buffer holds 9 or 18 planes
-  // Element strides of the state layout: population a of node (x, y) sits at
-  // y * rstride + (x >> 6) * tstride + a * pstride + (x & 63).  Tile-
-  // interleaved (default): the planes of one 64-column block of a row are
-  // contiguous, pstride = 64, tstride = planes * 64, rstride = planes * pitch.
-  // Plane-major: pstride = plane, tstride = 64, rstride = pitch.
+  // State layout: every x tile of tile_w columns (see below) owns one block
+  // of 64 slots per row and plane, the planes of a tile row contiguous.
+  // Population a of node (x, y) sits at
+  //   y * rstride + (x / tile_w) * tstride + a * pstride + lane_off + x % tile_w,
+  // i.e. in the slot of the lane that evaluates it; pstride = 64,
+  // tstride = planes * 64, rstride = planes * 64 * blocks per row.  The
+  // other slots of a block hold nothing that is read.
+  long long slots;  // slots per plane (64 * blocks per row * ny)
   long long pstride;
   int tstride;
   unsigned rstride;
@@ -78,7 +81,7 @@ __host__ __device__ inline bool default_scheme(const KParams &k) {
 __host__ __device__ inline bool buffer_fits(const KParams &k, int storage) {
   unsigned long long esz = (storage == kF32) ? 4ull : ((storage == kF16 || storage == kBF16) ? 2ull : 0ull);
   if (esz == 0) return false;
-  return 18ull * (unsigned long long)k.plane * esz < (1ull << 32);
+  return 18ull * (unsigned long long)k.slots * esz < (1ull << 32);
 }
 
 // FP32 copies of the launch constants (KParams::f32), rounded as the kernels

@@ -245,13 +245,17 @@ struct Col {
   int xc;         // column whose node this lane evaluates
   int xm, xp;     // source columns of links with e_x = +1 / -1
   unsigned oc, om, op;  // their element offsets within a stored row (state layout)
+  unsigned ow;          // the lane's slot in its wave's own block (stores)
+  bool wst;             // the lane stores that slot (buffer-addressed stores)
   bool outL, outR;  // those links come from outside (non-periodic x)
 };
 
 // Element offset of column x within a stored row of the state (see
-// KParams::pstride): 64-column blocks of tstride elements.
+// KParams::slots): the slot of the lane that evaluates x, in the block of
+// its x tile.
 __device__ __forceinline__ unsigned col_off(const KParams &k, int x) {
-  return (unsigned)(x >> 6) * (unsigned)k.tstride + (unsigned)(x & 63);
+  const unsigned t = (unsigned)x / (unsigned)k.tile_w;
+  return t * (unsigned)k.tstride + (unsigned)k.lane_off + ((unsigned)x - t * (unsigned)k.tile_w);
 }
 
 __device__ __forceinline__ Col make_col(const KParams &k, int xl) {
@@ -275,6 +279,8 @@ __device__ __forceinline__ Col make_col(const KParams &k, int xl) {
   c.oc = col_off(k, c.xc);
   c.om = col_off(k, c.xm);
   c.op = col_off(k, c.xp);
+  c.ow = c.oc;
+  c.wst = true;
   return c;
 }
 
@@ -310,7 +316,7 @@ __device__ __forceinline__ ConstPtr<R> const_table(const void *p) {
 // writes outside the buffer are dropped by the hardware.
 template <int S>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const void *p, const KParams &k) {
-  const unsigned bytes = (unsigned)(18ull * (unsigned long long)k.plane * sizeof(typename Store<S>::T));
+  const unsigned bytes = (unsigned)(18ull * (unsigned long long)k.slots * sizeof(typename Store<S>::T));
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
 template <int S>
@@ -756,7 +762,11 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
     cn.inv_tau_hf = cn.w1 * ((R)k.Pr - R(1));
   }
   collide<R, (S == kF32 || S == kF64)>(cn, s.q, s.f, s.h, s.m, Dx, Dy, ax, ay, P, Q);
-  if (!store) return;
+  // buffer-addressed stores cover every 128-byte line of the wave's block
+  // that holds one of its nodes (the halo lanes and lanes past nx write
+  // slots that are never read), so no store request fills a line in part;
+  // the others store the tile's own nodes
+  if (M == 2 ? !col.wst : !store) return;
   ST *dst = reinterpret_cast<ST *>(k.dst);
   // the node's number (y * pitch + x) keys the rounding generator; its
   // address follows the state layout
@@ -764,9 +774,9 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
   const unsigned hn = (S == kF16 || S == kBF16) ? sr_node(node, step) : 0u;
   const unsigned own = (unsigned)y * k.rstride + col.oc;
   if constexpr (M == 2) {
-    // row and plane in the scalar offset, the column in the vector offset
+    // row and plane in the scalar offset, the lane's slot in the vector offset
     const __amdgpu_buffer_rsrc_t r = state_rsrc<S>(k.dst, k);
-    const unsigned vb = col.oc * (unsigned)sizeof(ST);
+    const unsigned vb = col.ow * (unsigned)sizeof(ST);
     const unsigned rb = (unsigned)y * k.rstride * (unsigned)sizeof(ST);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -855,6 +865,18 @@ constexpr int kRowGroup = TCLBM_ROW_GROUP;
 #define TCLBM_BATCH32_OCC
 #endif
 
+// A lane's own-block slot and whether it stores it under buffer addressing:
+// the lanes of every 128-byte line (32 slots of FP32, 64 of 16-bit storage)
+// that holds one of the tile's nodes.
+template <int S>
+__device__ __forceinline__ void own_slot(const KParams &k, int xt, int lane, Col &col) {
+  col.ow = (unsigned)xt * (unsigned)k.tstride + (unsigned)lane;
+  const int valid = min(k.tile_w, k.nx - xt * k.tile_w);
+  const int last = k.lane_off + valid - 1;
+  constexpr int sh = (sizeof(typename Store<S>::T) == 2) ? 6 : 5;
+  col.wst = (lane >> sh) <= (last >> sh);
+}
+
 // The march of one wave over its (x tile, strip) of lattice k.
 template <int S, int M = 0>
 __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF *lds) {
@@ -865,7 +887,8 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
   const int r1 = min(r0 + k.strip_rows, k.ny);
   const int xl = xt * k.tile_w - k.lane_off + lane;
   const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
-  const Col col = make_col(k, xl);
+  Col col = make_col(k, xl);
+  own_slot<S>(k, xt, lane, col);
   const Consts<R> c = make_consts<R, M>(k);
   const bool yper = (k.bc[kYlo] == kPeriodic);
   const int ny = k.ny;
@@ -1031,7 +1054,8 @@ __device__ __forceinline__ void row_group(const KParams &k, int grp, int xt, int
   }
   const int xl = xt * k.tile_w - k.lane_off + lane;
   const bool store = (lane >= k.lane_off) && (lane < k.lane_off + k.tile_w) && (xl < k.nx);
-  const Col col = make_col(k, xl);
+  Col col = make_col(k, xl);
+  own_slot<S>(k, xt, lane, col);
   const Consts<R> c = make_consts<R, M>(k);
   // wave-uniform roles
   const bool edge_lo = E && (kind == 2 && w == 0), edge_hi = E && (kind == 3 && w == G - 1);

@@ -426,6 +426,31 @@ def test_instability_is_reported(T):
     lat.close()
 
 
+def test_x_periodicity_is_fixed_at_create(T):
+    """The x tiling of the state follows the x sides given at create, so
+    set_bc refuses to make a periodic x side closed or a closed one periodic,
+    and leaves the handle as it was; other changes of the sides are taken."""
+    case = W.uniform_noise(70, 20, seed=3)
+    say("case set_bc x periodicity 70x20")
+    lat = T.Lattice(case, storage="f32")
+    for side, kind in ((0, T.BOUNCEBACK), (1, T.BOUNCEBACK)):
+        with pytest.raises(T.TclbmError) as ei:
+            T.tclbm_set_bc(lat.h, side, kind)
+        assert ei.value.status == T.E_INVALID
+    T.tclbm_set_bc(lat.h, 2, T.WALL, 0.0, 0.0, 1.0)
+    T.tclbm_set_bc(lat.h, 3, T.WALL, 0.0, 0.0, 1.0)
+    lat.step(4)
+    lat.close()
+    closed = W.uniform_noise(70, 20, seed=3)
+    closed.bc = (T.BOUNCEBACK, T.BOUNCEBACK, 0, 0)
+    lat = T.Lattice(closed, storage="f32")
+    with pytest.raises(T.TclbmError) as ei:
+        T.tclbm_set_bc(lat.h, 0, T.PERIODIC)
+    assert ei.value.status == T.E_INVALID
+    lat.step(4)
+    lat.close()
+
+
 def test_batch_equals_members_alone_bitwise(T):
     """A batch of uneven lattices (walls, bounce-back, periodic, an adiabatic
     wall with per-node rates; one launch per step, members of both kernel

@@ -47,8 +47,9 @@ def test_null_handle_queries(T):
 def test_state_bytes_plan(T):
     p = T.tclbm_default_params(512, 256)
     nb = T.tclbm_state_bytes(p)
-    pitch, planes = 512, 18
-    buf = pitch * 256 * planes * 4
+    # one 64-slot block per x tile of 62 columns (periodic x) and plane
+    slots, planes = -(-512 // 62) * 64, 18
+    buf = slots * 256 * planes * 4
     assert nb >= 2 * buf
     assert nb - 2 * buf < 64 * 1024
     p.storage = T.STORE["f16"]
