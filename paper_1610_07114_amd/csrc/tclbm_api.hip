@@ -186,7 +186,7 @@ void fill_kparams(tclbm_ctx *c) {
 // Row-tiles per wave strip that the automatic strip height aims at, by storage
 // (one wave-row is one 62-column tile row; see decompose and batch_auto_rows).
 static long long strip_target(int storage) {
-  return (storage == kF32) ? 163840 : (storage == kF64 ? 65536 : 32768);
+  return (storage == kF32) ? 81920 : (storage == kF64 ? 65536 : 20480);
 }
 
 void decompose(tclbm_ctx *c) {
@@ -197,10 +197,10 @@ void decompose(tclbm_ctx *c) {
   if (rows <= 0) {
     // enough waves to fill 256 CUs many times over: strips of a few rows when
     // the lattice is large, down to a single row when it is small.  Halo rows
-    // are re-pulled once per strip, yet on 8192x4096 short strips measured
-    // fastest for FP32 (2 rows: 1252 us, 3: 1180, 4: 1204, 8: 1237, 33: 1414)
-    // while the 16-bit kernels prefer longer ones (FP16 4 rows: 919 us, 8: 839,
-    // 12: 816).
+    // are re-pulled once per strip, yet on 8192x4096 strips of 6-8 rows
+    // measured fastest for FP32 (2 rows: 1048 us, 3: 983, 4: 973, 6: 967,
+    // 8: 966, 16: 998, 32: 1024) and 24-32 rows for 16-bit storage (FP16
+    // 8 rows: 680 us, 16: 654, 24: 650, 32: 644, 48: 665).
     long long r = ((long long)k.ny * k.n_xtiles) / strip_target(c->p.storage);
     rows = (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
   }
@@ -807,8 +807,10 @@ struct tclbm_batch {
 };
 
 // Strip height for a whole batch: the single-lattice rule applied to the
-// members' row-tiles together (256 uneven RB lattices: FP32 2 rows and FP16
-// 13 rows, the fastest heights measured for that batch), capped at 32.
+// members' row-tiles together (256 uneven RB lattices: FP32 6 rows and FP16
+// 26, within 1% of the fastest heights measured for that batch: FP32 2 rows
+// 1004 us, 4: 946, 6: 937, 8: 939, 16: 989; FP16 16: 635, 24: 631, 32: 636),
+// capped at 32.
 static int batch_auto_rows(const tclbm_batch *b) {
   long long rowtiles = 0;
   for (tclbm_handle h : b->m) rowtiles += (long long)h->k.ny * h->k.n_xtiles;

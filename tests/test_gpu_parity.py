@@ -124,6 +124,23 @@ def test_decomposition_and_graphs_are_bitwise_neutral(T):
         assert np.array_equal(s, states[0])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_strip_heights_are_bitwise_neutral_with_walls(T, storage):
+    """Strips march up or down (odd strips clear of the walls go down); the
+    state after many steps is the same bitwise for every strip height."""
+    case = W.rayleigh_benard(nx=130, ny=37, seed=2, noise=1e-3)
+    say(f"case strip heights 130x37 walled {storage}, 60 steps")
+    states = []
+    for rows in (1, 2, 3, 4, 7, 16, 37):
+        lat = T.Lattice(case, storage=storage)
+        lat.set_tuning(rows, 0)
+        lat.step(60)
+        states.append(lat.read_state())
+        lat.close()
+    for rows, st in zip((2, 3, 4, 7, 16, 37), states[1:]):
+        assert np.array_equal(st, states[0]), rows
+
+
 def test_couette_fp64_20000_steps(T):
     case = W.couette()
     say("case couette 8x32 fp64 20000 steps")
