@@ -461,6 +461,36 @@ def bench_table3(torch, tclbm):
     return out
 
 
+def bench_persistent(torch, tclbm):
+    """Persistent batched launches (up to 256 steps per cooperative launch,
+    a grid barrier between steps) against the default per-step launches
+    replayed from 32-step graphs, on a small serving-sized batch, RB 512x256
+    and the 256-lattice batch: device microseconds per step, best of two."""
+    from paper_1610_07114_amd import workloads as W
+    sets = [("8 x RB 64x32, f16", [W.rayleigh_benard(nx=64, ny=32, seed=i, noise=1e-3) for i in range(8)], "f16",
+             2048),
+            ("RB 512x256, f32", [W.rayleigh_benard(nx=512, ny=256, seed=0)], "f32", 2048),
+            ("256 batched RB lattices, f32", [W.rb_from_spec(x) for x in W.batched_rb_specs(256, seed=0)], "f32",
+             128)]
+    stream = torch.cuda.Stream()
+    out = {}
+    for name, cases, storage, n in sets:
+        lats = [tclbm.Lattice(c, storage=storage, stream=stream) for c in cases]
+        b = tclbm.Batch(lats)
+        b.set_graph_chunk(32)
+        r = {}
+        for mode, steps in (("graph_us_per_step", 0), ("persistent_us_per_step", 256)):
+            b.set_persistent(steps)
+            b.step(64)
+            r[mode] = round(min(b.step_timed(n) for _ in range(2)) / n * 1e3, 2)
+        r["persistent_kernel"] = b.kernel
+        out[name] = r
+        b.close()
+        for lat in lats:
+            lat.close()
+    return out
+
+
 def single_extra(torch, tclbm, name, storage, steps, warmup, traffic_json, reduce_every=1000):
     """A single-lattice figure measured beside the headline: MLUPS over `steps`
     steps (FP64 sums every `reduce_every`) and the roofline of its kernel."""
@@ -554,6 +584,8 @@ def main():
                 out["roofline_large"][st] = single_extra(torch, tclbm, "large", st, 1000, 200, args.traffic_json)
             log("bench: Section 5D Table 3 sweep, internal-energy DF, FP32 batch of five lattices")
             out["table3"] = bench_table3(torch, tclbm)
+            log("bench: persistent batched launches vs per-step graph replays")
+            out["persistent_batch"] = bench_persistent(torch, tclbm)
             log("bench: HBM copy ceiling, 2 GiB -> 2 GiB")
             ceil = copy_probe(torch, tclbm)
             out["hbm_ceiling"] = ceil

@@ -300,9 +300,27 @@ tclbm_status tclbm_batch_set_graph_chunk(tclbm_batch_handle b, int32_t chunk);
  * height.  Synchronizes the stream.  Returns TCLBM_E_INVALID for rows < 0. */
 tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows);
 int32_t tclbm_batch_strip_rows(tclbm_batch_handle b);  /* height in use */
+/* Persistent launches: with steps_per_launch > 0, tclbm_batch_step runs the
+ * time steps of Sections 2-4 for every member in launches of up to that many
+ * steps each, instead of one launch per step.  The launch is cooperative (the
+ * runtime refuses a grid that cannot be resident at once); its blocks meet at
+ * a grid barrier between steps.  Results are identical to the per-step path.
+ * wait_us bounds a block's wait at a barrier (0: one second): a block that
+ * waits longer flags the launch and every block leaves, so a launch always
+ * ends; the steps it counted then leave the members' states undefined, the
+ * members are marked unstable and the next tclbm_batch_step returns
+ * TCLBM_E_STATE (tclbm_batch_step_timed reports TCLBM_E_DEVICE itself).
+ * Under stream capture the batch records per-step launches.  steps_per_launch
+ * = 0 returns to per-step launches.  TCLBM_E_INVALID for negative arguments,
+ * FP64 storage, or a member off the default scheme or beyond buffer
+ * addressing (4 GiB of state); TCLBM_E_DEVICE without cooperative launch. */
+tclbm_status tclbm_batch_set_persistent(tclbm_batch_handle b, int32_t steps_per_launch, int32_t wait_us);
+int32_t tclbm_batch_persistent(tclbm_batch_handle b);  /* steps per launch, 0: per-step launches */
 /* Name of the kernel a batch step launches ("batch_step_kernel_f32",
- * "batch_step_kernel" for 16-bit storage, "batch_step_kernel_f64"), as a
- * kernel trace shows it; a static string, NULL for a NULL batch. */
+ * "batch_step_kernel" for 16-bit storage, "batch_step_kernel_f64"; with
+ * persistent launches "batch_persistent_kernel_f32" or
+ * "batch_persistent_kernel"), as a kernel trace shows it; a static string,
+ * NULL for a NULL batch. */
 const char *tclbm_batch_step_kernel(tclbm_batch_handle b);
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b);
 

@@ -803,6 +803,13 @@ struct tclbm_batch {
   int strip_rows;      // the height in use
   bool all_default;    // every member runs the default scheme (leaner kernel)
   bool all_fit;        // every member's state buffers allow buffer addressing
+  // persistent launches (tclbm_batch_set_persistent)
+  int persist_steps;       // steps per launch (0: one launch per step)
+  int persist_max_grid;    // blocks that fit on the device at once
+  long long wait_ticks;    // longest barrier wait, wall-clock ticks
+  PersistCtl *d_ctl;       // barrier counter and failure word
+  unsigned *h_fail;        // pinned copy of the failure word after each launch
+  unsigned arrive_base;    // barrier arrivals so far
   char err[256];
 };
 
@@ -871,10 +878,52 @@ static tclbm_status batch_launch(tclbm_batch *b, int64_t n, int64_t *done) {
   return TCLBM_OK;
 }
 
+// A persistent launch whose barrier wait ran out leaves every member's state
+// undefined: the members are marked unstable and the batch refuses to step.
+static bool batch_persist_failed(tclbm_batch *b) {
+  if (!b->h_fail || __atomic_load_n(b->h_fail, __ATOMIC_ACQUIRE) == 0u) return false;
+  for (tclbm_handle h : b->m) h->unstable = true;
+  snprintf(b->err, sizeof(b->err),
+           "persistent batch: a block waited longer than the barrier limit; the members' states are undefined");
+  return true;
+}
+
+// n steps in launches of at most persist_steps steps each
+static tclbm_status batch_persist_run(tclbm_batch *b, int64_t n, int64_t *done) {
+  const int nwork = (b->total_waves + step_waves_per_block() - 1) / step_waves_per_block();
+  const int grid = nwork < b->persist_max_grid ? nwork : b->persist_max_grid;
+  while (n > 0) {
+    const int k = (int)(n < b->persist_steps ? n : b->persist_steps);
+    hipError_t e = launch_batch_persistent(b->d_tab, b->d_start, (int)b->m.size(), b->total_waves, b->storage,
+                                           b->parity, k, b->d_ctl, b->arrive_base, b->wait_ticks, grid, b->stream);
+    if (e != hipSuccess) {
+      snprintf(b->err, sizeof(b->err), "persistent batch launch: %s", hipGetErrorString(e));
+      return TCLBM_E_DEVICE;
+    }
+    b->arrive_base += (unsigned)(k - 1) * (unsigned)grid;
+    b->parity ^= (k & 1);
+    *done += k;
+    n -= k;
+    e = hipMemcpyAsync(b->h_fail, &b->d_ctl->fail, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) {
+      snprintf(b->err, sizeof(b->err), "persistent batch: %s", hipGetErrorString(e));
+      return TCLBM_E_DEVICE;
+    }
+  }
+  return TCLBM_OK;
+}
+
 // Enqueue n steps: replays of the captured chunk while at least two chunks
 // remain (after one plain step if the parity is odd), plain launches for the
 // rest.  *done counts the steps actually enqueued, also on a failure.
 static tclbm_status batch_run(tclbm_batch *b, int64_t n, int64_t *done) {
+  if (b->persist_steps > 0) {
+    // a cooperative launch cannot be recorded into a graph: under stream
+    // capture the batch records per-step launches instead
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(b->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+      return batch_persist_run(b, n, done);
+  }
   const int ch = b->stream ? b->graph_chunk : 0;
   if (ch >= 2 && n >= 2 * (int64_t)ch) {
     if (b->parity) {
@@ -953,10 +1002,18 @@ tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_ha
   b->strip_rows_req = 0;
   hipError_t e = hipMalloc(&b->d_tab, sizeof(KParams) * 2 * n);
   if (e == hipSuccess) e = hipMalloc(&b->d_start, sizeof(int) * (n + 1));
-  if (e == hipSuccess) e = batch_upload(b);
+  if (e == hipSuccess) e = hipMalloc(&b->d_ctl, sizeof(PersistCtl));
+  if (e == hipSuccess) e = hipMemset(b->d_ctl, 0, sizeof(PersistCtl));
+  if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_fail, sizeof(unsigned), hipHostMallocDefault);
+  if (e == hipSuccess) {
+    *b->h_fail = 0u;
+    e = batch_upload(b);
+  }
   if (e != hipSuccess) {
     if (b->d_tab) hipFree(b->d_tab);
     if (b->d_start) hipFree(b->d_start);
+    if (b->d_ctl) hipFree(b->d_ctl);
+    if (b->h_fail) hipHostFree(b->h_fail);
     delete b;
     return TCLBM_E_DEVICE;
   }
@@ -966,6 +1023,7 @@ tclbm_status tclbm_batch_create(tclbm_handle *members, int32_t n, tclbm_batch_ha
 
 tclbm_status tclbm_batch_step(tclbm_batch_handle b, int64_t nsteps) {
   if (!b || nsteps < 0) return TCLBM_E_INVALID;
+  if (batch_persist_failed(b)) return TCLBM_E_STATE;
   for (size_t i = 0; i < b->m.size(); ++i) {
     tclbm_handle h = b->m[i];
     if (h->unstable) return TCLBM_E_STATE;
@@ -1007,7 +1065,8 @@ tclbm_status tclbm_batch_step_timed(tclbm_batch_handle b, int64_t nsteps, double
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != TCLBM_OK) return st;
-  return e == hipSuccess ? TCLBM_OK : TCLBM_E_DEVICE;
+  if (e != hipSuccess) return TCLBM_E_DEVICE;
+  return batch_persist_failed(b) ? TCLBM_E_DEVICE : TCLBM_OK;
 }
 
 int32_t tclbm_batch_size(tclbm_batch_handle b) { return b ? (int32_t)b->m.size() : -1; }
@@ -1034,7 +1093,38 @@ tclbm_status tclbm_batch_set_strip_rows(tclbm_batch_handle b, int32_t rows) {
 
 int32_t tclbm_batch_strip_rows(tclbm_batch_handle b) { return b ? b->strip_rows : -1; }
 
-const char *tclbm_batch_step_kernel(tclbm_batch_handle b) { return b ? batch_step_kernel_name(b->storage) : nullptr; }
+tclbm_status tclbm_batch_set_persistent(tclbm_batch_handle b, int32_t steps_per_launch, int32_t wait_us) {
+  if (!b || steps_per_launch < 0 || wait_us < 0) return TCLBM_E_INVALID;
+  if (steps_per_launch == 0) {
+    b->persist_steps = 0;
+    return TCLBM_OK;
+  }
+  if (b->storage == kF64 || !b->all_default || !b->all_fit) {
+    snprintf(b->err, sizeof(b->err),
+             "persistent batch: FP32 or 16-bit storage, every member on the default scheme and within 4 GiB");
+    return TCLBM_E_INVALID;
+  }
+  int dev = 0, coop = 0, khz = 0, maxb = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e == hipSuccess) e = persistent_max_blocks(b->storage, &maxb);
+  if (e != hipSuccess || !coop || khz <= 0 || maxb <= 0) {
+    snprintf(b->err, sizeof(b->err), "persistent batch: no cooperative launch on this device");
+    return TCLBM_E_DEVICE;
+  }
+  b->persist_steps = steps_per_launch;
+  b->persist_max_grid = maxb;
+  b->wait_ticks = (long long)(wait_us > 0 ? wait_us : 1000000) * khz / 1000;
+  return TCLBM_OK;
+}
+
+int32_t tclbm_batch_persistent(tclbm_batch_handle b) { return b ? b->persist_steps : -1; }
+
+const char *tclbm_batch_step_kernel(tclbm_batch_handle b) {
+  if (!b) return nullptr;
+  return b->persist_steps > 0 ? batch_persistent_kernel_name(b->storage) : batch_step_kernel_name(b->storage);
+}
 
 tclbm_status tclbm_batch_destroy(tclbm_batch_handle b) {
   if (!b) return TCLBM_E_INVALID;
@@ -1042,6 +1132,8 @@ tclbm_status tclbm_batch_destroy(tclbm_batch_handle b) {
   batch_drop_graph(b);
   (void)hipFree(b->d_tab);
   (void)hipFree(b->d_start);
+  (void)hipFree(b->d_ctl);
+  (void)hipHostFree(b->h_fail);
   delete b;
   return TCLBM_OK;
 }

@@ -122,6 +122,17 @@ const char *batch_step_kernel_name(int storage);
 // one step of every lattice in a device-side descriptor table (see tclbm_batch_*)
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
                              int storage, int parity, bool all_default, bool all_fit, hipStream_t s);
+// Persistent batch: barrier state in device memory (zeroed at creation)
+struct PersistCtl {
+  unsigned arrive;  // barrier arrivals so far (grows by the grid size per barrier)
+  unsigned fail;    // set by a block that waited too long; stays set
+};
+// blocks of the persistent kernel that fit on the device at once
+hipError_t persistent_max_blocks(int storage, int *blocks);
+hipError_t launch_batch_persistent(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
+                                   int storage, int parity, int nsteps, PersistCtl *ctl, unsigned base,
+                                   long long wait_ticks, int grid, hipStream_t s);
+const char *batch_persistent_kernel_name(int storage);
 hipError_t launch_init(const KParams &k, int storage, const double *d_rho, const double *d_ux,
                        const double *d_uy, const double *d_T, hipStream_t s);
 // fields (device, double, nx*ny each, nullable) and per-block partial sums

@@ -1130,8 +1130,8 @@ __global__ __launch_bounds__(64 * kStepWaves) void step_kernel_f64(KParams k) {
 // compiled in; MB = 0: chosen per member.
 template <int S, int MB>
 __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, const int *__restrict__ wave_start,
-                                           int n_inst, int parity) {
-  const int wave = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kStepWaves + (threadIdx.x >> 6));
+                                           int n_inst, int parity, int lblock) {
+  const int wave = __builtin_amdgcn_readfirstlane(lblock * kStepWaves + (threadIdx.x >> 6));
   if (wave >= wave_start[n_inst]) return;
   int lo = 0, hi = n_inst - 1;  // last instance whose start <= wave
   while (lo < hi) {
@@ -1161,18 +1161,126 @@ __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, cons
 template <int S, int MB>
 __global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH_OCC void batch_step_kernel(
     const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity) {
-  batch_body<S, MB>(tab, wave_start, n_inst, parity);
+  batch_body<S, MB>(tab, wave_start, n_inst, parity, xcd_block(blockIdx.x, gridDim.x));
 }
 template <int MB>
 __global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH32_OCC void batch_step_kernel_f32(
     const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity) {
-  batch_body<kF32, MB>(tab, wave_start, n_inst, parity);
+  batch_body<kF32, MB>(tab, wave_start, n_inst, parity, xcd_block(blockIdx.x, gridDim.x));
 }
 template <int MB>
 __global__ __launch_bounds__(64 * kStepWaves) void batch_step_kernel_f64(const KParams *__restrict__ tab,
                                                                          const int *__restrict__ wave_start,
                                                                          int n_inst, int parity) {
-  batch_body<kF64, MB>(tab, wave_start, n_inst, parity);
+  batch_body<kF64, MB>(tab, wave_start, n_inst, parity, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Persistent batched steps: one cooperative launch (the runtime refuses a
+// grid whose blocks cannot all be resident at once) runs nsteps steps of every
+// member.  Its blocks take the per-step grid's logical blocks in turn, strided
+// by the grid size, and meet at a grid barrier between steps.  The barrier is
+// an arrival counter that only grows (the launch is told the count it starts
+// from; comparisons are modulo 2^32) and a failure word that stays set.  A
+// block that waits longer than wait_ticks of the wall clock at a barrier sets
+// the failure word and leaves; every other block leaves at its next barrier,
+// and a launch that finds the word set runs no step, so every wave ends.
+// Agent-scope fences around the barrier make the stores of one step visible
+// to the loads of the next across the XCDs' separate L2 caches.  That is an
+// L2 write-back per block and barrier, where a kernel boundary needs one per
+// XCD: on MI355X these launches measured slower than per-step launches
+// replayed from a graph (512x256: 85 vs 9.2 us per step; 256 lattices: 1504
+// vs 940 us), so they are not the default.
+// Only the lean default-scheme instantiation with buffer addressing (MB = 2).
+__device__ __forceinline__ bool persist_flag_clear(PersistCtl *ctl) {
+  __shared__ int clear;
+  __syncthreads();
+  if (threadIdx.x == 0) clear = __hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  __syncthreads();
+  return clear != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(PersistCtl *ctl, unsigned target, long long wait_ticks) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    // one wave per block fences for the whole block (every wave of it waited
+    // for its stores above): release of the block's stores to every XCD
+    __threadfence();
+    int good = 1;
+    __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while ((int)(__hip_atomic_load(&ctl->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      if (__hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+          wall_clock64() - t0 >= wait_ticks) {
+        __hip_atomic_store(&ctl->fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();  // acquire, for the caches the block's waves share
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <int S>
+__device__ __forceinline__ void persist_body(const KParams *__restrict__ tab, const int *__restrict__ wave_start,
+                                             int n_inst, int parity, int nsteps, PersistCtl *ctl, unsigned base,
+                                             long long wait_ticks) {
+  if (!persist_flag_clear(ctl)) return;
+  const int nwork = (wave_start[n_inst] + kStepWaves - 1) / kStepWaves;
+  const int G = gridDim.x;
+  const int lb0 = xcd_block(blockIdx.x, G);
+  for (int s = 0; s < nsteps; ++s) {
+    for (int lb = lb0; lb < nwork; lb += G) batch_body<S, 2>(tab, wave_start, n_inst, parity ^ (s & 1), lb);
+    if (s + 1 < nsteps && !grid_barrier(ctl, base + (unsigned)(s + 1) * (unsigned)G, wait_ticks)) return;
+  }
+}
+
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH32_OCC void batch_persistent_kernel_f32(
+    const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity, int nsteps,
+    PersistCtl *ctl, unsigned base, long long wait_ticks) {
+  persist_body<kF32>(tab, wave_start, n_inst, parity, nsteps, ctl, base, wait_ticks);
+}
+template <int S>
+__global__ __launch_bounds__(64 * kStepWaves) TCLBM_BATCH_OCC void batch_persistent_kernel(
+    const KParams *__restrict__ tab, const int *__restrict__ wave_start, int n_inst, int parity, int nsteps,
+    PersistCtl *ctl, unsigned base, long long wait_ticks) {
+  persist_body<S>(tab, wave_start, n_inst, parity, nsteps, ctl, base, wait_ticks);
+}
+
+static const void *persistent_kernel(int storage) {
+  switch (storage) {
+    case kF32: return reinterpret_cast<const void *>(&batch_persistent_kernel_f32);
+    case kF16: return reinterpret_cast<const void *>(&batch_persistent_kernel<kF16>);
+    case kBF16: return reinterpret_cast<const void *>(&batch_persistent_kernel<kBF16>);
+    default: return nullptr;
+  }
+}
+
+hipError_t persistent_max_blocks(int storage, int *blocks) {
+  *blocks = 0;
+  const void *f = persistent_kernel(storage);
+  if (!f) return hipErrorInvalidValue;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * kStepWaves, 0);
+  if (e == hipSuccess) *blocks = per_cu * cus;
+  return e;
+}
+
+hipError_t launch_batch_persistent(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
+                                   int storage, int parity, int nsteps, PersistCtl *ctl, unsigned base,
+                                   long long wait_ticks, int grid, hipStream_t s) {
+  const void *f = persistent_kernel(storage);
+  if (!f || grid <= 0 || nsteps <= 0 || total_waves <= 0) return hipErrorInvalidValue;
+  void *args[] = {(void *)&d_tab, (void *)&d_wave_start, (void *)&n_inst, (void *)&parity, (void *)&nsteps,
+                  (void *)&ctl,   (void *)&base,         (void *)&wait_ticks};
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(64 * kStepWaves), args, 0, s);
 }
 
 hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int n_inst, int total_waves,
@@ -1209,6 +1317,15 @@ hipError_t launch_batch_step(const KParams *d_tab, const int *d_wave_start, int 
 }
 
 int step_waves_per_block() { return kStepWaves; }
+
+const char *batch_persistent_kernel_name(int storage) {
+  switch (storage) {
+    case kF32: return "batch_persistent_kernel_f32";
+    case kF16:
+    case kBF16: return "batch_persistent_kernel";
+    default: return "";
+  }
+}
 
 const char *batch_step_kernel_name(int storage) {
   switch (storage) {

@@ -57,7 +57,8 @@ EXPORTS = ["tclbm_default_params", "tclbm_state_bytes", "tclbm_create", "tclbm_s
            "tclbm_step_kernel", "tclbm_destroy", "tclbm_status_str", "tclbm_last_error", "tclbm_hbm_copy",
            "tclbm_batch_create", "tclbm_batch_step", "tclbm_batch_step_timed", "tclbm_batch_size",
            "tclbm_batch_waves", "tclbm_batch_set_graph_chunk", "tclbm_batch_set_strip_rows",
-           "tclbm_batch_strip_rows", "tclbm_batch_step_kernel", "tclbm_batch_destroy"]
+           "tclbm_batch_strip_rows", "tclbm_batch_set_persistent", "tclbm_batch_persistent",
+           "tclbm_batch_step_kernel", "tclbm_batch_destroy"]
 
 
 def _load():
@@ -120,6 +121,10 @@ def _load():
     lib.tclbm_batch_set_strip_rows.restype = ctypes.c_int
     lib.tclbm_batch_strip_rows.argtypes = [H]
     lib.tclbm_batch_strip_rows.restype = ctypes.c_int32
+    lib.tclbm_batch_set_persistent.argtypes = [H, ctypes.c_int32, ctypes.c_int32]
+    lib.tclbm_batch_set_persistent.restype = ctypes.c_int
+    lib.tclbm_batch_persistent.argtypes = [H]
+    lib.tclbm_batch_persistent.restype = ctypes.c_int32
     lib.tclbm_batch_step_kernel.argtypes = [H]
     lib.tclbm_batch_step_kernel.restype = ctypes.c_char_p
     lib.tclbm_batch_destroy.argtypes = [H]
@@ -267,6 +272,14 @@ def tclbm_batch_strip_rows(b) -> int:
     return int(_lib.tclbm_batch_strip_rows(b))
 
 
+def tclbm_batch_set_persistent(b, steps_per_launch: int, wait_us: int = 0):
+    _chk(_lib.tclbm_batch_set_persistent(b, int(steps_per_launch), int(wait_us)))
+
+
+def tclbm_batch_persistent(b) -> int:
+    return int(_lib.tclbm_batch_persistent(b))
+
+
 def tclbm_batch_step_kernel(b) -> str:
     return _lib.tclbm_batch_step_kernel(b).decode()
 
@@ -378,6 +391,15 @@ class Batch:
     @property
     def strip_rows(self) -> int:
         return tclbm_batch_strip_rows(self.h)
+
+    def set_persistent(self, steps_per_launch: int, wait_us: int = 0):
+        """Run up to steps_per_launch steps per (cooperative) launch; 0: one
+        launch per step."""
+        tclbm_batch_set_persistent(self.h, steps_per_launch, wait_us)
+
+    @property
+    def persistent(self) -> int:
+        return tclbm_batch_persistent(self.h)
 
     @property
     def kernel(self) -> str:
