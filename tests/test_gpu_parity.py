@@ -430,10 +430,14 @@ def test_conservation_sums_fp64(T):
     assert s1.momy == pytest.approx(s0.momy + 64 * s0.mass * case.ay, rel=1e-10)
 
 
-def test_instability_is_reported(T):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_instability_is_reported(T, storage):
+    """A state driven unstable is reported by the moments reduction (FP16
+    storage: a deviation beyond the half range is stored as inf) and the
+    handle refuses further steps."""
     case = W.uniform_noise(64, 64, seed=1, amp_u=0.45, amp_T=0.6, tau_f=0.501, pointwise=0.2)
-    say("case deliberately unstable state 64x64 (NaN arithmetic only)")
-    lat = T.Lattice(case, storage="f32")
+    say(f"case deliberately unstable state 64x64 {storage} (NaN arithmetic only)")
+    lat = T.Lattice(case, storage=storage)
     lat.step(400)
     _, _, _, _, s, st = T.tclbm_moments(lat.h, case.nx, case.ny, True, check=False)
     assert st == T.E_UNSTABLE
