@@ -269,8 +269,9 @@ const char *tclbm_step_kernel(tclbm_handle h);
  * NULL handle. */
 tclbm_status tclbm_destroy(tclbm_handle h);
 
-/* Diagnostic: enqueue one plain streaming copy of `bytes` (multiple of 16,
- * 16-byte aligned device pointers, non-overlapping) on the stream.  Used to
+/* Diagnostic: enqueue one streaming copy of `bytes` (multiple of 16, 16-byte
+ * aligned device pointers, non-overlapping) on the stream, with the access
+ * types of the step kernels (plain loads, non-temporal stores).  Used to
  * measure the achievable HBM bandwidth next to the step kernel and to scale
  * hardware byte counters. */
 tclbm_status tclbm_hbm_copy(void *dst, const void *src, size_t bytes, void *hip_stream);

@@ -272,7 +272,7 @@ def test_16bit_storage_keeps_steady_nusselt(T, storage):
     assert max(errs) < tol
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_rb512_nusselt_vs_fp64(T, storage):
     """512x256 Rayleigh-Benard, Ra 1e5, Pr 0.71, 2e5 steps: Nu every 1000 steps
     against the stored FP64 oracle history (end value and window mean)."""
