@@ -24,8 +24,11 @@ the same run (unless --no-extras):
   shock_tube      the 8192x4 shock tube
   roofline_large  the step kernel on an 8192x4096 lattice (HBM-resident
                   state) with FP32, FP16 and BF16 storage
-  hbm_ceiling     a plain chunked 2 GiB copy on the same GPU; the HBM-resident
-                  figures also state their fraction of it
+  table3          Section 5D's Nu(Ra) sweep with the internal-energy DF
+  persistent_batch  persistent batched launches against per-step graph replays
+  hbm_ceiling     a 2 GiB streaming copy on the same GPU with the step kernels'
+                  access types; the HBM-resident figures also state their
+                  fraction of it
   serving         seeded Poisson streams of RB/Couette solve requests served
                   with continuous batching and FP16 or BF16 storage (solves/s,
                   p50/p99 latency, Nu error of requests restarted from FP64
@@ -168,9 +171,10 @@ def cpu_baseline_detail(seconds_target: float = 3.0) -> dict:
 
 # ------------------------------------------------------------------- probes ---
 def copy_probe(torch, tclbm, nbytes: int = 2 << 30, reps: int = 20):
-    """Achievable HBM bandwidth of a plain streaming copy (read + write bytes per
-    launch / launch time; each block copies one contiguous 16 KiB chunk), the
-    measured ceiling beside the 8 TB/s peak."""
+    """Achievable HBM bandwidth of a streaming copy with the step kernels'
+    access types (one 16-byte element per thread, plain load, non-temporal
+    store; read + write bytes per launch / launch time), the measured ceiling
+    beside the 8 TB/s peak."""
     dev = torch.device("cuda:0")
     s = torch.cuda.Stream(dev)
     with torch.cuda.stream(s):
