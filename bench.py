@@ -231,7 +231,7 @@ def bench_single(torch, tclbm, case, storage, steps, warmup, reduce_every, strip
 
 # -------------------------------------------------------------------- batch ---
 def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=200, reduce_every=1000,
-                strip_rows=0, graph_chunk=None, traffic_json=None):
+                strip_rows=0, graph_chunk=None, traffic_json=None, persistent=0):
     """The batched workload: n seeded 2N x N Rayleigh-Benard lattices (N
     log-uniform on [32, 512], Ra log-uniform on [1e4, 1e6], Pr uniform on
     [0.5, 7]; draws below the scheme's linear stability limit 1/w1 = 0.55 are
@@ -242,7 +242,9 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
     replay graphs.  Timed: exactly `steps` steps, with the FP64 sums of every
     member after each `reduce_every` of them; HIP events on the batch's stream
     bracket the same steps.  `traffic` is the stored counter measurement for
-    the strip height in use."""
+    the strip height in use.  persistent > 0: persistent launches of up to
+    that many steps each instead (no traffic figure: the counters were taken
+    on the per-step kernel)."""
     from paper_1610_07114_amd import serving as S
     from paper_1610_07114_amd import workloads as W
     rejected = []
@@ -268,6 +270,8 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
     cap = (steps // 2) // 2 * 2
     chunk = min(chunk, cap) if cap >= 2 else 0
     b.set_graph_chunk(chunk)
+    if persistent > 0:
+        b.set_persistent(persistent)
     rows_in_use = b.strip_rows
     b.step(warmup)
     torch.cuda.synchronize(dev)
@@ -305,7 +309,8 @@ def bench_batch(torch, tclbm, n=256, seed=0, storage="f32", steps=1000, warmup=2
             "redrawn_below_stability_limit": len(rejected), "strip_rows": rows_in_use,
             "roofline": roofline(bpl, nodes, dev_ms / 1e3 / steps,
                                  load_traffic(traffic_json, f"batched_rayleigh_benard_{n}_{storage}_rows{rows_in_use}")
-                                 if traffic_json else None, kernel=kernel)}
+                                 if traffic_json and persistent <= 0 else None, kernel=kernel),
+            "persistent_steps_per_launch": persistent}
 
 
 # ------------------------------------------------------------------ serving ---
@@ -519,6 +524,8 @@ def main():
     ap.add_argument("--batch-strip-rows", type=int, default=0,
                     help="batch workload: fixed strip height (with --graph-chunk) instead of the autotuner")
     ap.add_argument("--graph-chunk", type=int, default=32)
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="batch workload: persistent launches of up to this many steps each")
     ap.add_argument("--requests", type=int, default=500, help="serving stream length")
     ap.add_argument("--serve-storage", default="f16,bf16", help="storage forms of the serving streams")
     ap.add_argument("--time-units", type=float, default=1.0, help="serving request length in flow times")
@@ -565,7 +572,7 @@ def main():
         b = bench_batch(torch, tclbm, storage=args.storage, steps=args.steps, warmup=args.warmup,
                         reduce_every=args.reduce_every, strip_rows=args.batch_strip_rows,
                         graph_chunk=args.graph_chunk if args.batch_strip_rows > 0 else None,
-                        traffic_json=args.traffic_json)
+                        traffic_json=args.traffic_json, persistent=args.persistent)
         out = {"metric": "TCLBM MLUPS", "value": b["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
@@ -575,7 +582,8 @@ def main():
                           "unstable_instances": b["unstable_instances"],
                           "redrawn_below_stability_limit": b["redrawn_below_stability_limit"],
                           "strip_rows": b["strip_rows"], "graph_chunk": b["graph_chunk"],
-                          "device_ms": b["device_ms"], "autotune": b["autotune"]},
+                          "device_ms": b["device_ms"], "autotune": b["autotune"],
+                          **({"persistent_steps_per_launch": args.persistent} if args.persistent > 0 else {})},
                "roofline": b["roofline"]}
         if not args.no_extras:
             log("bench: RB 512x256 fp32, 2000 steps")
