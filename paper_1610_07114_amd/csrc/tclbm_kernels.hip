@@ -817,6 +817,8 @@ __device__ __forceinline__ void collide_store(const KParams &k, const Consts<typ
 //   TCLBM_ROW_GROUP           rows per block for FP32 lattices of single-row
 //                             strips, neighbours' u_y(1 - theta) shared in LDS
 //                             (4; 1: one independent wave per row)
+//   TCLBM_BATCH_ALT_MARCH     batch kernels: odd interior strips march
+//                             downwards (1)
 #ifndef TCLBM_STEP_WAVES
 #define TCLBM_STEP_WAVES 4
 #endif
@@ -853,6 +855,10 @@ constexpr int kStepWaves = TCLBM_STEP_WAVES;
 #ifndef TCLBM_ROW_GROUP
 #define TCLBM_ROW_GROUP 4
 #endif
+#ifndef TCLBM_BATCH_ALT_MARCH
+#define TCLBM_BATCH_ALT_MARCH 1
+#endif
+constexpr bool kBatchAlt = TCLBM_BATCH_ALT_MARCH;
 constexpr int kRowGroup = TCLBM_ROW_GROUP;
 #if TCLBM_BATCH_WAVES_PER_EU > 0
 #define TCLBM_BATCH_OCC __attribute__((amdgpu_waves_per_eu(TCLBM_BATCH_WAVES_PER_EU, TCLBM_BATCH_WAVES_PER_EU)))
@@ -887,7 +893,7 @@ __device__ __forceinline__ void own_slot(const KParams &k, int xt, int lane, Col
 }
 
 // The march of one wave over its (x tile, strip) of lattice k.
-template <int S, int M = 0>
+template <int S, int M = 0, bool Alt = false>
 __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF *lds) {
   using R = typename Real<S>::T;
   const int strip = wave / k.n_xtiles;
@@ -930,7 +936,23 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
     collide_store<S, M>(k, c, r0, col, store, cur, R(0.5) * (hi.qy - lo.qy), xl, step);
     return;
   }
-  if (!yper && r0 == 0) {
+  // Alt (the batch kernels): an odd strip whose rows and halo rows are all
+  // pulled fluid rows marches downwards (d = -1).  It then pulls the rows it
+  // shares with each neighbouring strip at the same end of the march as that
+  // neighbour does, so the second pull of a shared row finds it in L2 (the
+  // 256-lattice batch: counted reads 1.41x -> 1.07x of the algorithmic
+  // bytes, 902 -> 895 us per step).  On one large lattice the strips that
+  // share a row run too far apart for that, and it measured slower (8192x4096
+  // 929 -> 945 us).  Each row's collision depends only on its own and its two
+  // neighbouring rows, so the result does not depend on the direction.
+  const bool down = Alt && (strip & 1) && r1 - r0 >= 2 && (yper || (r0 >= 2 && r1 <= ny - 2));
+  const int d = down ? -1 : 1;
+  if (down) {
+    get_row<S, M>(k, c, r1 == ny ? 0 : r1, col, nxt);  // row above the strip
+    qy_m1 = nxt.qy;
+    get_row<S, M>(k, c, r1 - 1, col, cur);
+    j = r1 - 1;
+  } else if (!yper && r0 == 0) {
     // bottom edge: row 0 needs u(1-theta) of rows 1 and 2 (one-sided difference)
     get_row<S, M>(k, c, 1, col, nxt);                       // row 1 (ny >= 3: a fluid row)
     RowState<R> two;
@@ -968,25 +990,29 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
   // FP32 storage pipelines the pulls through two LDS slots: the row the next
   // iteration needs is loaded while this one collides.
   constexpr bool kAsync = (S == kF32) && TCLBM_LDS_PULL;
-  bool pending = false;  // the loads of row j + 1 are in lds slot `slot`
+  bool pending = false;  // the loads of the march's next row are in lds slot `slot`
   int slot = 0;
+  // the row after y in the march's direction (periodic wrap)
+  const auto step_row = [&](int y) { return d > 0 ? (y == ny - 1 ? 0 : y + 1) : (y == 0 ? ny - 1 : y - 1); };
   const auto next_pulled = [&](int jj) {
-    // row jj + 1 is pulled (not derived) by iteration jj of this strip
+    // the row after jj is pulled (not derived) by iteration jj of this strip
+    if (d < 0) return jj >= r0;
     if (jj >= r1 || (!yper && jj == ny - 1)) return false;
     const int y1 = (jj == ny - 1) ? 0 : jj + 1;
     return yper || !is_wall_row(k, y1);
   };
   if (kAsync && next_pulled(j)) {
-    pull_issue_lds<M>(k, (j == ny - 1) ? 0 : j + 1, col, lds);
+    pull_issue_lds<M>(k, step_row(j), col, lds);
     pending = true;
   }
-  for (; j < r1; ++j) {
+  const int jend = d > 0 ? r1 : r0 - 1;
+  for (; j != jend; j += d) {
     if (!yper && j == ny - 1) {  // top edge: one-sided difference with the rows below
       const R Dy = R(0.5) * (R(3) * cur.qy - R(4) * qy_m1 + qy_m2);
       collide_store<S, M>(k, c, j, col, store, cur, Dy, xl, step);
       break;
     }
-    const int yn = (j == ny - 1) ? 0 : j + 1;
+    const int yn = step_row(j);
     if constexpr (kAsync) {
       if (pending) {
         lds_wait_loads();
@@ -997,18 +1023,19 @@ __device__ __forceinline__ void march(const KParams &k, int wave, int lane, LdsF
         get_row<S, M>(k, c, yn, col, nxt);
       }
       pending = false;
-      if (next_pulled(j + 1)) {
+      if (next_pulled(j + d)) {
         // the other slot was last read an iteration ago
         lds_wait_reads();
         slot ^= 1;
-        pull_issue_lds<M>(k, (yn == ny - 1) ? 0 : yn + 1, col, lds + slot * kLdsSlot);
+        pull_issue_lds<M>(k, step_row(yn), col, lds + slot * kLdsSlot);
         pending = true;
       }
     } else {
       if (!yper && is_wall_row(k, yn)) get_wall_row<S, M>(k, c, yn, col, cur, nxt);
       else get_row<S, M>(k, c, yn, col, nxt);
     }
-    const R Dy = R(0.5) * (nxt.qy - qy_m1);
+    // central difference, row above minus row below, whichever way the march goes
+    const R Dy = R(0.5) * (d > 0 ? nxt.qy - qy_m1 : qy_m1 - nxt.qy);
     collide_store<S, M>(k, c, j, col, store, cur, Dy, xl, step);
     qy_m2 = qy_m1;
     qy_m1 = cur.qy;
@@ -1159,10 +1186,11 @@ __device__ __forceinline__ void batch_body(const KParams *__restrict__ tab, cons
     lds = (LdsF *)(buf + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 2 * kLdsSlot);
   }
   if constexpr (MB >= 1) {
-    march<S, MB>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+    march<S, MB, kBatchAlt>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
   } else {
-    if (TCLBM_SCHEME_SPECIAL && default_scheme(k)) march<S, 1>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
-    else march<S, 0>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+    if (TCLBM_SCHEME_SPECIAL && default_scheme(k))
+      march<S, 1, kBatchAlt>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
+    else march<S, 0, kBatchAlt>(k, wave - wave_start[lo], threadIdx.x & 63, lds);
   }
 }
 
